@@ -1,0 +1,58 @@
+"""Plants plausible mistakes in a copy of the oracle (on the CPU) and checks
+that the oracle pins reject every one of them.
+
+A starting value of 1 for the node-power loop is not planted: it is
+equivalent, since floor(a) = floor(b) = 0 for midpoints in [0, 1)."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    # merge takes from the right on ties (unstable)
+    "unstable_merge": ("int take_right = (i >= mid) || (j < hi && less_at(A, j, i));",
+                       "int take_right = (i >= mid) || (j < hi && !less_at(A, i, j));"),
+    # weakly (not strictly) decreasing runs are reversed
+    "nonstrict_descending_run": ("if (e < n && less_at(A, e, e - 1)) {\n        while (e < n && less_at(A, e, e - 1)) e++;",
+                                 "if (e < n && !less_at(A, e - 1, e)) {\n        while (e < n && !less_at(A, e - 1, e)) e++;"),
+    # midpoint without the half run length
+    "midpoint_drops_half_length": ("unsigned __int128 an = 2 * (unsigned __int128)s1 + n1;",
+                                   "unsigned __int128 an = 2 * (unsigned __int128)s1;"),
+    # pops only on a power gap of two or more
+    "stack_pop_condition": ("while (S->top > 0 && S->ps[S->top - 1] > p) {",
+                            "while (S->top > 0 && S->ps[S->top - 1] > p + 1) {"),
+    # min-run extension one element too long
+    "min_run_off_by_one": ("uint64_t ew = (s + w < n) ? s + w : n;",
+                           "uint64_t ew = (s + w + 1 < n) ? s + w + 1 : n;"),
+    # insertion sort moves past equal keys
+    "insertion_sort_unstable": ("while (j > s && key_less(A, v, A->key + (j - 1) * A->ks)) {",
+                                "while (j > s && !key_less(A, A->key + (j - 1) * A->ks, v)) {"),
+    # merge cost counts only the right run
+    "merge_cost_right_only": ("S->M += hi - lo;", "S->M += hi - mid;"),
+    # negative floats in increasing bit order
+    "float_negative_order": ("return a > b;                 /* both negative",
+                             "return a < b;                 /* both negative"),
+    # midpoints of the wrong runs
+    "power_swapped_runs": ("unsigned p = node_power(S->s1, S->e1 - S->s1, s2, e2 - s2, S->n);",
+                           "unsigned p = node_power(S->s1, e2 - s2, s2, S->e1 - S->s1, S->n);"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_planted_mistake(tmp_path, name):
+    a, b = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "powersort_oracle.c")).read()
+    assert a in src, "mutation site not found"
+    ign = shutil.ignore_patterns("*.so", "*.tmp", "__pycache__")
+    for d in ("oracle", "tests", "paper_1805_04154_amd"):
+        shutil.copytree(os.path.join(ROOT, d), tmp_path / d, ignore=ign)
+    (tmp_path / "oracle" / "powersort_oracle.c").write_text(src.replace(a, b))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 1, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
