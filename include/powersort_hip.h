@@ -1,0 +1,145 @@
+/*
+ * powersort_hip.h -- C ABI of the MI355X (gfx950) powersort library.
+ *
+ * Powersort is the stable natural mergesort of Munro & Wild, "Nearly-Optimal
+ * Mergesorts: Fast, Practical Sorting Methods That Optimally Adapt to
+ * Existing Runs" (ESA 2018).  It
+ *   - splits the input into runs (Sec. 2: maximal weakly increasing blocks, or
+ *     strictly decreasing blocks, which are reversed), extending runs shorter
+ *     than a minimum run length w by insertion sort (App. B.3/B.4);
+ *   - gives every boundary between adjacent runs its node power
+ *     (Def. "Node Power");
+ *   - merges adjacent runs stably in the order of the min-oriented Cartesian
+ *     tree of the powers (Cor. "Cartesian tree", Alg. PowerSort), whose merge
+ *     cost M = sum of merge result sizes (Sec. 2.2) is at most H n + 2 n
+ *     (Thm. "powersort").
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* and the key/payload arrays are DEVICE pointers of the
+ *     current HIP device; everything else is host memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it; results are valid once the stream has been
+ *     synchronised.  Argument checks happen before anything is enqueued: an
+ *     error status means nothing was launched.
+ *   - The caller owns every array passed in.  Unless ps_options.workspace is
+ *     given, the library keeps one scratch allocation per stream (grown on
+ *     demand, reused across calls) until ps_release(stream).
+ *   - Calls on one stream are serialised by the stream; calls on different
+ *     streams use different scratch memory and may overlap.
+ *   - Keys: int32, uint32, int64, uint64 in their natural order; float32 in
+ *     IEEE-754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN;
+ *     NaNs ordered by payload bits).  Output keys keep their bit patterns.
+ *   - Limits: n_total < 2^32 elements per call, every segment < 2^31.
+ *   - No exceptions or aborts cross this ABI.
+ */
+#ifndef POWERSORT_HIP_H
+#define POWERSORT_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PS_OK = 0,
+    PS_ERR_INVALID_ARG = -1,   /* null pointer, bad key type, bad segment offsets, ... */
+    PS_ERR_TOO_LARGE = -2,     /* a segment >= 2^31 or n_total >= 2^32 */
+    PS_ERR_OUT_OF_MEMORY = -3, /* scratch allocation failed (nothing enqueued) */
+    PS_ERR_HIP = -4,           /* a HIP runtime call failed; see ps_last_error() */
+    PS_ERR_UNSUPPORTED = -5    /* option outside the supported range (e.g. min_run > 64) */
+} ps_status;
+
+typedef enum {
+    PS_KEY_I32 = 0,
+    PS_KEY_U32 = 1,
+    PS_KEY_I64 = 2,
+    PS_KEY_U64 = 3,
+    PS_KEY_F32 = 4
+} ps_key_type;
+
+/* Options; a NULL pointer means all defaults.  struct_size must be
+ * sizeof(ps_options). */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t min_run;          /* w of App. B.3/B.4; 0 = default 24 (the paper's
+                                  setting); 1 = pure natural runs; at most 64 */
+    uint32_t flags;            /* reserved, must be 0 */
+    uint32_t reserved;
+    void *workspace;           /* optional caller-owned device scratch */
+    uint64_t workspace_bytes;  /* its size; must be >= ps_workspace_bytes(...) */
+} ps_options;
+
+/* Bytes of device scratch one call needs for n_total elements in
+ * num_segments segments (ps_sort: num_segments = 1).  has_payload is 0 or 1.
+ * Returns 0 for invalid arguments. */
+size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
+                          const ps_options *opt);
+
+/* Sort keys[0..n) ascending and stably with powersort, in place; payload
+ * (nullable, uint32 per key) is permuted alongside.  Sec. 2 (problem
+ * statement and run convention), Alg. PowerSort, App. B.
+ * d_merge_cost (nullable, 1 x uint64) receives the merge cost M of
+ * Sec. 2.2: the sum of the result sizes of all r - 1 merges. */
+ps_status ps_sort(void *keys, uint32_t *payload, uint64_t n, ps_key_type key_type, const ps_options *opt,
+                  uint64_t *d_merge_cost, void *stream);
+
+/* Sort each segment [d_offsets[g], d_offsets[g+1]) independently, as a whole
+ * powersort with its own n and origin (the paper's nodePower takes the
+ * subarray bounds, App. B.4), all segments in one batch of launches.
+ * d_offsets: num_segments + 1 uint64 on the device, non-decreasing, with
+ * d_offsets[0] = 0 and d_offsets[num_segments] = n_total.  Empty segments are
+ * allowed.  d_merge_costs (nullable): num_segments uint64, M per segment.
+ * d_status (nullable, 1 x int32): receives PS_OK, or PS_ERR_INVALID_ARG /
+ * PS_ERR_TOO_LARGE when the offsets fail validation on the device; in that
+ * case the keys are left in an unspecified order (no out-of-bounds access). */
+ps_status ps_segmented_sort(void *keys, uint32_t *payload, const uint64_t *d_offsets, uint64_t num_segments,
+                            uint64_t n_total, ps_key_type key_type, const ps_options *opt,
+                            uint64_t *d_merge_costs, int32_t *d_status, void *stream);
+
+/* Merge cost M (Sec. 2.2) that ps_sort would incur on keys[0..n), computed
+ * from the run partition, the node powers and the merge tree alone; keys
+ * are not modified and no data moves.  d_merge_cost: 1 x uint64. */
+ps_status ps_merge_cost(const void *keys, uint64_t n, ps_key_type key_type, const ps_options *opt,
+                        uint64_t *d_merge_cost, void *stream);
+
+/* Per-segment merge costs of ps_segmented_sort without sorting.
+ * d_merge_costs: num_segments uint64.  d_status as in ps_segmented_sort. */
+ps_status ps_segmented_merge_cost(const void *keys, const uint64_t *d_offsets, uint64_t num_segments,
+                                  uint64_t n_total, ps_key_type key_type, const ps_options *opt,
+                                  uint64_t *d_merge_costs, int32_t *d_status, void *stream);
+
+/* Intermediate results of the method, for tests and tools (device arrays,
+ * capacities in elements).  Leaves are the runs after min-run extension;
+ * boundary j (1 <= j < r) separates leaves j-1 and j. */
+typedef struct {
+    uint32_t *starts;      /* n_total + 1: leaf starts, starts[r] = n_total */
+    uint8_t *powers;       /* n_total + 1: powers[j] (Def. "Node Power"); 0 at
+                              j = 0, j = r and between segments */
+    uint32_t *node_left;   /* n_total: first leaf below node j */
+    uint32_t *node_right;  /* n_total: one past the last leaf below node j */
+    uint8_t *leaf_depth;   /* n_total: depth of leaf i in its segment's tree */
+    uint32_t *r;           /* 1: number of leaves */
+} ps_inspect_out;
+
+/* Runs the non-moving part of the method (partition, powers, tree) on keys
+ * and copies its intermediate arrays into `out` (each member nullable).
+ * d_offsets may be NULL for one segment [0, n_total). */
+ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_segments, uint64_t n_total,
+                     ps_key_type key_type, const ps_options *opt, ps_inspect_out *out, void *stream);
+
+/* Free the scratch memory the library holds for `stream` (synchronises it). */
+ps_status ps_release(void *stream);
+
+/* Static description of a status code. */
+const char *ps_status_string(ps_status status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POWERSORT_HIP_H */

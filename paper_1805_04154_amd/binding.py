@@ -1,0 +1,206 @@
+"""Thin ctypes binding of the powersort HIP library (include/powersort_hip.h).
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the current HIP stream; every step of the method runs in the library's
+kernels.  There is no fallback: if the library is missing or a call fails,
+an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpowersort_hip.so")
+
+PS_OK = 0
+STATUS_NAMES = {0: "PS_OK", -1: "PS_ERR_INVALID_ARG", -2: "PS_ERR_TOO_LARGE", -3: "PS_ERR_OUT_OF_MEMORY",
+                -4: "PS_ERR_HIP", -5: "PS_ERR_UNSUPPORTED"}
+KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, torch.float32: 4}
+
+# Every symbol include/powersort_hip.h declares.
+EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_segmented_sort", "ps_merge_cost", "ps_segmented_merge_cost",
+           "ps_inspect", "ps_release", "ps_status_string", "ps_last_error")
+
+
+class PsOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("min_run", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class PsInspectOut(ctypes.Structure):
+    _fields_ = [("starts", ctypes.c_void_p), ("powers", ctypes.c_void_p), ("node_left", ctypes.c_void_p),
+                ("node_right", ctypes.c_void_p), ("leaf_depth", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+
+
+class PowersortError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpowersort_hip.so (built by paper_1805_04154_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1805_04154_amd.build` "
+                          "(the sort has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    opt = ctypes.POINTER(PsOptions)
+    lib.ps_workspace_bytes.restype = ctypes.c_size_t
+    lib.ps_workspace_bytes.argtypes = [u64, u64, i32, i32, opt]
+    lib.ps_sort.restype = i32
+    lib.ps_sort.argtypes = [vp, vp, u64, i32, opt, vp, vp]
+    lib.ps_segmented_sort.restype = i32
+    lib.ps_segmented_sort.argtypes = [vp, vp, vp, u64, u64, i32, opt, vp, vp, vp]
+    lib.ps_merge_cost.restype = i32
+    lib.ps_merge_cost.argtypes = [vp, u64, i32, opt, vp, vp]
+    lib.ps_segmented_merge_cost.restype = i32
+    lib.ps_segmented_merge_cost.argtypes = [vp, vp, u64, u64, i32, opt, vp, vp, vp]
+    lib.ps_inspect.restype = i32
+    lib.ps_inspect.argtypes = [vp, vp, u64, u64, i32, opt, ctypes.POINTER(PsInspectOut), vp]
+    lib.ps_release.restype = i32
+    lib.ps_release.argtypes = [vp]
+    lib.ps_status_string.restype = ctypes.c_char_p
+    lib.ps_status_string.argtypes = [i32]
+    lib.ps_last_error.restype = ctypes.c_char_p
+    lib.ps_last_error.argtypes = []
+    _ = u32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != PS_OK:
+        msg = _lib.ps_last_error().decode()
+        raise PowersortError(status, msg)
+
+
+def _opts(min_run: int | None, workspace: torch.Tensor | None = None):
+    if min_run is None and workspace is None:
+        return None
+    o = PsOptions(ctypes.sizeof(PsOptions), int(min_run or 0), 0, 0, None, 0)
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return ctypes.byref(o)
+
+
+def _key_type(t: torch.Tensor) -> int:
+    if t.dtype not in KEY_TYPES:
+        raise TypeError(f"unsupported key dtype {t.dtype}")
+    return KEY_TYPES[t.dtype]
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def workspace_bytes(n_total: int, num_segments: int, dtype: torch.dtype, has_payload: bool,
+                    min_run: int | None = None) -> int:
+    lib = load_library()
+    return int(lib.ps_workspace_bytes(n_total, num_segments, KEY_TYPES[dtype], int(has_payload),
+                                      _opts(min_run)))
+
+
+def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int | None = None,
+         merge_cost: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None):
+    """Stable in-place powersort of a 1-D device tensor (payload permuted alongside).
+
+    merge_cost: optional 1-element int64 device tensor that receives M (as uint64 bits)."""
+    lib = load_library()
+    _dev_check(keys, payload, merge_cost)
+    if payload is not None and (payload.dtype not in (torch.int32, torch.uint32) or payload.numel() != keys.numel()):
+        raise ValueError("payload must be a 32-bit tensor with one entry per key")
+    _check(lib.ps_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None, keys.numel(),
+                       _key_type(keys), _opts(min_run, workspace),
+                       merge_cost.data_ptr() if merge_cost is not None else None, _stream(stream)))
+    return keys, payload
+
+
+def segmented_sort(keys: torch.Tensor, payload: torch.Tensor | None, offsets: torch.Tensor,
+                   min_run: int | None = None, merge_costs: torch.Tensor | None = None,
+                   status: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None):
+    """Sort every segment [offsets[g], offsets[g+1]) independently (offsets: int64 device tensor)."""
+    lib = load_library()
+    _dev_check(keys, payload, offsets, merge_costs, status)
+    nseg = offsets.numel() - 1
+    _check(lib.ps_segmented_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None,
+                                 offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
+                                 _opts(min_run, workspace),
+                                 merge_costs.data_ptr() if merge_costs is not None else None,
+                                 status.data_ptr() if status is not None else None, _stream(stream)))
+    return keys, payload
+
+
+def merge_cost(keys: torch.Tensor, min_run: int | None = None, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+    """Merge cost M of powersort on keys (keys untouched); returns a 1-element int64 device tensor."""
+    lib = load_library()
+    _dev_check(keys)
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=keys.device)
+    _check(lib.ps_merge_cost(keys.data_ptr(), keys.numel(), _key_type(keys), _opts(min_run), out.data_ptr(),
+                             _stream(stream)))
+    return out
+
+
+def segmented_merge_cost(keys: torch.Tensor, offsets: torch.Tensor, min_run: int | None = None,
+                         out: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    lib = load_library()
+    _dev_check(keys, offsets)
+    nseg = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(nseg, dtype=torch.int64, device=keys.device)
+    _check(lib.ps_segmented_merge_cost(keys.data_ptr(), offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
+                                       _opts(min_run), out.data_ptr(),
+                                       status.data_ptr() if status is not None else None, _stream(stream)))
+    return out
+
+
+def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: int | None = None,
+            stream=None) -> dict:
+    """Leaf starts, powers, node leaf ranges and leaf depths (as device tensors, trimmed to r)."""
+    lib = load_library()
+    _dev_check(keys, offsets)
+    n = keys.numel()
+    dev = keys.device
+    starts = torch.zeros(n + 1, dtype=torch.int32, device=dev)
+    powers = torch.zeros(n + 1, dtype=torch.uint8, device=dev)
+    left = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    right = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    depth = torch.zeros(max(n, 1), dtype=torch.uint8, device=dev)
+    r = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = PsInspectOut(starts.data_ptr(), powers.data_ptr(), left.data_ptr(), right.data_ptr(), depth.data_ptr(),
+                       r.data_ptr())
+    nseg = 1 if offsets is None else offsets.numel() - 1
+    _check(lib.ps_inspect(keys.data_ptr(), offsets.data_ptr() if offsets is not None else None, nseg, n,
+                          _key_type(keys), _opts(min_run), ctypes.byref(out), _stream(stream)))
+    rr = int(r.item())
+    return {"r": rr, "starts": starts[: rr + 1], "powers": powers[: rr + 1], "node_left": left[:rr],
+            "node_right": right[:rr], "leaf_depth": depth[:rr]}
+
+
+def release(stream=None):
+    lib = load_library()
+    _check(lib.ps_release(_stream(stream)))

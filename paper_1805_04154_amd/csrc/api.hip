@@ -1,0 +1,483 @@
+// C ABI of the powersort library: argument checks, workspace layout, the
+// per-stream scratch pool and the launch sequence.
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "../../include/powersort_hip.h"
+#include "common.hpp"
+#include "block.hpp"
+#include "internal.hpp"
+
+namespace ps {
+
+constexpr size_t kCountersBytes = sizeof(Counters);
+constexpr int kMaskBlockA = kThreads * 16;
+
+// ------------------------------------------------------------ small kernels
+
+// Copies the caller's segment offsets into the workspace, checking that they
+// start at 0, never decrease, end at n_total and describe segments < 2^31.
+// Invalid offsets are replaced by one segment [0, n_total) and reported
+// through the status word (so that no later kernel can index out of bounds).
+__global__ __launch_bounds__(kThreads) void offsets_kernel(const uint64_t* __restrict__ in, uint32_t nseg,
+                                                            uint64_t N, uint64_t* __restrict__ out,
+                                                            int32_t* __restrict__ status) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    int my = 0;
+    for (uint32_t g = threadIdx.x; g <= nseg; g += kThreads) {
+        const uint64_t v = in ? in[g] : (g == 0 ? 0 : N);
+        if (g == 0 && v != 0) my |= 1;
+        if (g == nseg && v != N) my |= 1;
+        if (g > 0) {
+            const uint64_t u = in ? in[g - 1] : 0;
+            if (v < u) my |= 1;
+            else if (v - u > kMaxSegment) my |= 2;
+        }
+    }
+    if (my) atomicOr(&bad, my);
+    __syncthreads();
+    for (uint32_t g = threadIdx.x; g <= nseg; g += kThreads) {
+        uint64_t v = in ? in[g] : (g == 0 ? 0 : N);
+        if (bad) v = (g == 0) ? 0 : N;
+        out[g] = v;
+    }
+    if (threadIdx.x == 0 && status)
+        *status = (bad & 1) ? (int32_t)PS_ERR_INVALID_ARG : (bad & 2) ? (int32_t)PS_ERR_TOO_LARGE : (int32_t)PS_OK;
+}
+
+__global__ void copy_u64_kernel(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+template <class T>
+__global__ void copy_dyn_kernel(const T* __restrict__ src, T* __restrict__ dst, const uint32_t* __restrict__ r_dev,
+                                uint32_t extra, uint32_t cap) {
+    const uint32_t n = min(cap, *r_dev + extra);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ layout
+
+struct Layout {
+    size_t total = 0;
+    size_t scratch_keys, scratch_pay, offsets;
+    size_t code[4], cnt[4], entry[4], offs[4];
+    uint32_t ntab[4];
+    int levels;
+    size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt;
+    size_t unit_a, unit_b, unit_par, bigleaf, bigleaf_mode, bucket, bucket_tile, leaf_tile;
+    uint32_t rmax;
+};
+
+static size_t take(size_t& at, size_t bytes) {
+    at = (at + 255) & ~(size_t)255;
+    const size_t here = at;
+    at += bytes;
+    return here;
+}
+
+static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_t w, bool moves) {
+    Layout L;
+    size_t at = 0;
+    L.scratch_keys = moves ? take(at, N * kb) : 0;
+    L.scratch_pay = (moves && hp) ? take(at, N * 4) : 0;
+    L.offsets = take(at, (nseg + 1) * 8);
+    const uint32_t W1 = w + 1;
+    uint32_t nt = (uint32_t)((N + kPartTile - 1) / kPartTile);
+    L.levels = 0;
+    while (true) {
+        L.ntab[L.levels] = nt;
+        L.code[L.levels] = take(at, (size_t)nt * W1);
+        L.cnt[L.levels] = take(at, (size_t)nt * W1 * 4);
+        L.entry[L.levels] = take(at, nt);
+        L.offs[L.levels] = take(at, (size_t)nt * 4);
+        L.levels++;
+        if (nt <= (uint32_t)kScanGroup) break;
+        nt = (nt + kScanGroup - 1) / kScanGroup;
+    }
+    const uint64_t per = (w < 2) ? 2 : w;
+    uint64_t rmax = N / per + nseg + 1;
+    if (rmax > N) rmax = N;
+    L.rmax = (uint32_t)rmax;
+    const size_t r1 = rmax + 1;
+    const size_t nb = (rmax + kMaskBlockA - 1) / kMaskBlockA + 1;
+    L.counters = take(at, kCountersBytes);
+    L.starts = take(at, r1 * 4);
+    L.Q = take(at, r1 * 8);
+    L.P = take(at, r1 + 1);
+    L.leaf_depth = take(at, r1);
+    L.node_depth = take(at, r1);
+    L.aggF = take(at, nb * 16);
+    L.aggB = take(at, nb * 16);
+    L.inF = take(at, nb * 8);
+    L.inB = take(at, nb * 8);
+    L.mc = take(at, (nseg + 1) * 8);
+    L.Lf = take(at, r1 * 4);
+    L.Rt = take(at, r1 * 4);
+    if (moves) {
+        L.unit_a = take(at, r1 * 4);
+        L.unit_b = take(at, r1 * 4);
+        L.unit_par = take(at, r1);
+        L.bigleaf = take(at, r1 * 4);
+        L.bigleaf_mode = take(at, r1);
+        L.bucket = take(at, r1 * 4);
+        L.bucket_tile = take(at, r1 * 4);
+        L.leaf_tile = take(at, r1 * 4);
+    } else {
+        L.unit_a = L.unit_b = L.unit_par = L.bigleaf = L.bigleaf_mode = L.bucket = L.bucket_tile = L.leaf_tile = 0;
+    }
+    L.total = take(at, 0) + 256;
+    return L;
+}
+
+// -------------------------------------------------------------- scratch pool
+
+struct PoolEntry {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+};
+static std::mutex g_pool_mu;
+static std::unordered_map<void*, PoolEntry> g_pool;  // keyed by stream
+static thread_local std::string g_last_error;
+
+static ps_status fail(ps_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+static ps_status hip_fail(hipError_t e, const char* where) {
+    return fail(PS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* opt, void** out) {
+    if (opt && opt->workspace) {
+        if (opt->workspace_bytes < bytes) return fail(PS_ERR_INVALID_ARG, "workspace smaller than ps_workspace_bytes()");
+        *out = opt->workspace;
+        return PS_OK;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PoolEntry& p = g_pool[(void*)st];
+    if (p.ptr && p.bytes >= bytes && p.device == dev) {
+        *out = p.ptr;
+        return PS_OK;
+    }
+    if (p.ptr) {
+        // The old block may still be in use by work queued on this stream.
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(p.ptr);
+        p.ptr = nullptr;
+        p.bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    const size_t want = bytes + bytes / 8;  // headroom against regrowth
+    void* ptr = nullptr;
+    e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    p.ptr = ptr;
+    p.bytes = want;
+    p.device = dev;
+    *out = ptr;
+    return PS_OK;
+}
+
+// ------------------------------------------------------------------ driver
+
+enum class Mode { Sort, Cost, Inspect };
+
+struct Call {
+    void* keys;
+    uint32_t* payload;
+    const uint64_t* d_offsets;  // nullable: one segment
+    uint64_t nseg;
+    uint64_t N;
+    int kt;
+    uint32_t w;
+    uint64_t* d_costs;          // nullable
+    int32_t* d_status;          // nullable
+    ps_inspect_out* inspect;    // Mode::Inspect
+    Mode mode;
+};
+
+static size_t key_bytes(int kt) { return (kt == KT_I64 || kt == KT_U64) ? 8 : 4; }
+
+static ps_status check_common(int kt, const ps_options* opt, uint32_t* w) {
+    if (kt < KT_I32 || kt > KT_F32) return fail(PS_ERR_INVALID_ARG, "unknown key type");
+    *w = 24;
+    if (opt) {
+        if (opt->struct_size != sizeof(ps_options)) return fail(PS_ERR_INVALID_ARG, "ps_options.struct_size mismatch");
+        if (opt->flags != 0) return fail(PS_ERR_UNSUPPORTED, "ps_options.flags must be 0");
+        if (opt->min_run) *w = opt->min_run;
+    }
+    if (*w > (uint32_t)kMaxMinRun) return fail(PS_ERR_UNSUPPORTED, "min_run above 64 is not supported");
+    return PS_OK;
+}
+
+static inline uint32_t ilog2_floor(uint64_t x) {
+    uint32_t l = 0;
+    while (x >>= 1) ++l;
+    return l;
+}
+
+static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
+    const uint32_t N = (uint32_t)c.N;
+    const uint32_t nseg = (uint32_t)c.nseg;
+    const bool moves = (c.mode == Mode::Sort);
+    const bool hp = moves && c.payload != nullptr;
+    const size_t kb = key_bytes(c.kt);
+    const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves);
+    void* ws = nullptr;
+    ps_status s = get_workspace(st, L.total, opt, &ws);
+    if (s != PS_OK) return s;
+    char* base = (char*)ws;
+    auto at = [&](size_t off) { return (void*)(base + off); };
+
+    uint64_t* offsets = (uint64_t*)at(L.offsets);
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, nseg, c.N, offsets, c.d_status);
+    Counters* cnt = (Counters*)at(L.counters);
+    uint64_t* mc = (uint64_t*)at(L.mc);
+    hipError_t e = launch_init(cnt, mc, nseg, st);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+
+    PartitionArgs pa{};
+    pa.keys = c.keys;
+    pa.N = N;
+    pa.offsets = offsets;
+    pa.nseg = nseg;
+    pa.w = c.w;
+    pa.levels = L.levels;
+    for (int l = 0; l < L.levels; ++l) {
+        pa.code[l] = (uint8_t*)at(L.code[l]);
+        pa.cnt[l] = (uint32_t*)at(L.cnt[l]);
+        pa.entry[l] = (uint8_t*)at(L.entry[l]);
+        pa.offs[l] = (uint32_t*)at(L.offs[l]);
+        pa.ntab[l] = L.ntab[l];
+    }
+    pa.starts = (uint32_t*)at(L.starts);
+    pa.r_dev = (uint32_t*)cnt;  // Counters.r is its first word
+    pa.rmax = L.rmax;
+    e = launch_partition(c.kt, pa, st);
+    if (e != hipSuccess) return hip_fail(e, "partition launch");
+
+    TreeArgs ta{};
+    ta.keys = c.keys;
+    ta.offsets = offsets;
+    ta.nseg = nseg;
+    ta.rmax = L.rmax;
+    ta.starts = pa.starts;
+    ta.cnt = cnt;
+    ta.Q = (uint64_t*)at(L.Q);
+    ta.P = (uint8_t*)at(L.P);
+    ta.leaf_depth = (uint8_t*)at(L.leaf_depth);
+    ta.node_depth = (uint8_t*)at(L.node_depth);
+    ta.aggF = (Mask2*)at(L.aggF);
+    ta.aggB = (Mask2*)at(L.aggB);
+    ta.inF = (uint64_t*)at(L.inF);
+    ta.inB = (uint64_t*)at(L.inB);
+    ta.mc = mc;
+    ta.Lf = (uint32_t*)at(L.Lf);
+    ta.Rt = (uint32_t*)at(L.Rt);
+    e = launch_tree_cost(ta, st);
+    if (e != hipSuccess) return hip_fail(e, "tree launch");
+
+    if (c.mode == Mode::Inspect) {
+        e = launch_node_ranges(ta, st);
+        if (e != hipSuccess) return hip_fail(e, "node-range launch");
+    }
+    if (moves) {
+        ta.lists.unit_a = (uint32_t*)at(L.unit_a);
+        ta.lists.unit_b = (uint32_t*)at(L.unit_b);
+        ta.lists.unit_par = (uint8_t*)at(L.unit_par);
+        ta.lists.bigleaf = (uint32_t*)at(L.bigleaf);
+        ta.lists.bigleaf_mode = (uint8_t*)at(L.bigleaf_mode);
+        ta.lists.bucket = (uint32_t*)at(L.bucket);
+        ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
+        ta.lists.leaf_tile = (uint32_t*)at(L.leaf_tile);
+        e = launch_node_ranges(ta, st);
+        if (e == hipSuccess) e = launch_tree_lists(c.kt, ta, st);
+        if (e != hipSuccess) return hip_fail(e, "tree-list launch");
+        MoveArgs ma{};
+        ma.keys[0] = c.keys;
+        ma.keys[1] = at(L.scratch_keys);
+        ma.pay[0] = c.payload;
+        ma.pay[1] = hp ? (uint32_t*)at(L.scratch_pay) : nullptr;
+        ma.starts = pa.starts;
+        ma.P = ta.P;
+        ma.Lf = ta.Lf;
+        ma.Rt = ta.Rt;
+        ma.node_depth = ta.node_depth;
+        ma.cnt = cnt;
+        ma.unit_a = ta.lists.unit_a;
+        ma.unit_b = ta.lists.unit_b;
+        ma.unit_par = ta.lists.unit_par;
+        ma.bigleaf = ta.lists.bigleaf;
+        ma.bigleaf_mode = ta.lists.bigleaf_mode;
+        ma.bucket = ta.lists.bucket;
+        ma.bucket_tile = ta.lists.bucket_tile;
+        ma.leaf_tile = ta.lists.leaf_tile;
+        const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
+        const uint64_t max_units = c.N / 2 + 1;
+        const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, 2048);
+        e = launch_moves(c.kt, hp, ma, pmax, 1024, grid_fuse, 2048, st);
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+    }
+    if (c.d_costs) {
+        hipLaunchKernelGGL(copy_u64_kernel, dim3(std::min<uint32_t>(1024, (nseg + kThreads - 1) / kThreads + 1)),
+                           dim3(kThreads), 0, st, mc, c.d_costs, nseg);
+    }
+    if (c.mode == Mode::Inspect && c.inspect) {
+        const ps_inspect_out& o = *c.inspect;
+        const uint32_t* r_dev = (const uint32_t*)cnt;
+        const uint32_t cap = N + 1;
+        const dim3 g(1024), b(kThreads);
+        if (o.starts) hipLaunchKernelGGL(copy_dyn_kernel<uint32_t>, g, b, 0, st, pa.starts, o.starts, r_dev, 1u, cap);
+        if (o.powers) hipLaunchKernelGGL(copy_dyn_kernel<uint8_t>, g, b, 0, st, ta.P, o.powers, r_dev, 1u, cap);
+        if (o.node_left) hipLaunchKernelGGL(copy_dyn_kernel<uint32_t>, g, b, 0, st, ta.Lf, o.node_left, r_dev, 0u, N);
+        if (o.node_right) hipLaunchKernelGGL(copy_dyn_kernel<uint32_t>, g, b, 0, st, ta.Rt, o.node_right, r_dev, 0u, N);
+        if (o.leaf_depth)
+            hipLaunchKernelGGL(copy_dyn_kernel<uint8_t>, g, b, 0, st, ta.leaf_depth, o.leaf_depth, r_dev, 0u, N);
+        if (o.r) hipLaunchKernelGGL(copy_u32_kernel, dim3(1), dim3(64), 0, st, r_dev, o.r);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "launch");
+    return PS_OK;
+}
+
+// Degenerate inputs (n_total == 0) still report merge costs of zero and a
+// valid status, through the same small kernels.
+static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st) {
+    const Layout L = make_layout(0, c.nseg, key_bytes(c.kt), false, c.w, false);
+    void* ws = nullptr;
+    ps_status s = get_workspace(st, L.total, opt, &ws);
+    if (s != PS_OK) return s;
+    uint64_t* offsets = (uint64_t*)((char*)ws + L.offsets);
+    uint64_t* mc = (uint64_t*)((char*)ws + L.mc);
+    Counters* cnt = (Counters*)((char*)ws + L.counters);
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, (uint32_t)c.nseg, 0ull, offsets,
+                       c.d_status);
+    hipError_t e = launch_init(cnt, mc, (uint32_t)c.nseg, st);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    if (c.d_costs)
+        hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(kThreads), 0, st, mc, c.d_costs, (uint32_t)c.nseg);
+    if (c.mode == Mode::Inspect && c.inspect && c.inspect->r)
+        hipLaunchKernelGGL(copy_u32_kernel, dim3(1), dim3(64), 0, st, (const uint32_t*)cnt, c.inspect->r);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "launch");
+    return PS_OK;
+}
+
+static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
+    g_last_error.clear();
+    uint32_t w;
+    ps_status s = check_common(c.kt, opt, &w);
+    if (s != PS_OK) return s;
+    c.w = w;
+    if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^32");
+    if (c.nseg == 0) return fail(PS_ERR_INVALID_ARG, "num_segments must be at least 1");
+    if (c.nseg >= kMaxTotal) return fail(PS_ERR_TOO_LARGE, "too many segments");
+    if (!c.d_offsets && c.nseg != 1) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
+    if (!c.d_offsets && c.N > kMaxSegment) return fail(PS_ERR_TOO_LARGE, "n must be below 2^31");
+    if (c.N > 0 && !c.keys) return fail(PS_ERR_INVALID_ARG, "keys is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (c.N == 0) return run_empty(c, opt, st);
+    return run(c, opt, st);
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" {
+
+size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
+                          const ps_options* opt) {
+    uint32_t w;
+    if (check_common((int)key_type, opt, &w) != PS_OK) return 0;
+    if (n_total > kMaxTotal || num_segments == 0 || num_segments >= kMaxTotal) return 0;
+    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, w, true).total;
+}
+
+ps_status ps_sort(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_type, const ps_options* opt,
+                  uint64_t* d_merge_cost, void* stream) {
+    Call c{keys, payload, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
+    return dispatch(c, opt, stream);
+}
+
+ps_status ps_segmented_sort(void* keys, uint32_t* payload, const uint64_t* d_offsets, uint64_t num_segments,
+                            uint64_t n_total, ps_key_type key_type, const ps_options* opt, uint64_t* d_merge_costs,
+                            int32_t* d_status, void* stream) {
+    if (!d_offsets) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
+    Call c{keys, payload, d_offsets, num_segments, n_total, (int)key_type, 0, d_merge_costs, d_status, nullptr,
+           Mode::Sort};
+    return dispatch(c, opt, stream);
+}
+
+ps_status ps_merge_cost(const void* keys, uint64_t n, ps_key_type key_type, const ps_options* opt,
+                        uint64_t* d_merge_cost, void* stream) {
+    if (!d_merge_cost) return fail(PS_ERR_INVALID_ARG, "d_merge_cost is NULL");
+    Call c{(void*)keys, nullptr, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Cost};
+    return dispatch(c, opt, stream);
+}
+
+ps_status ps_segmented_merge_cost(const void* keys, const uint64_t* d_offsets, uint64_t num_segments,
+                                  uint64_t n_total, ps_key_type key_type, const ps_options* opt,
+                                  uint64_t* d_merge_costs, int32_t* d_status, void* stream) {
+    if (!d_offsets) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
+    if (!d_merge_costs) return fail(PS_ERR_INVALID_ARG, "d_merge_costs is NULL");
+    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, d_merge_costs, d_status,
+           nullptr, Mode::Cost};
+    return dispatch(c, opt, stream);
+}
+
+ps_status ps_inspect(const void* keys, const uint64_t* d_offsets, uint64_t num_segments, uint64_t n_total,
+                     ps_key_type key_type, const ps_options* opt, ps_inspect_out* out, void* stream) {
+    if (!out) return fail(PS_ERR_INVALID_ARG, "out is NULL");
+    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, nullptr, nullptr, out,
+           Mode::Inspect};
+    return dispatch(c, opt, stream);
+}
+
+ps_status ps_release(void* stream) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find(stream);
+    if (it == g_pool.end()) return PS_OK;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (it->second.ptr) {
+        e = hipFree(it->second.ptr);
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    g_pool.erase(it);
+    return PS_OK;
+}
+
+const char* ps_status_string(ps_status status) {
+    switch (status) {
+    case PS_OK: return "PS_OK";
+    case PS_ERR_INVALID_ARG: return "PS_ERR_INVALID_ARG: invalid argument";
+    case PS_ERR_TOO_LARGE: return "PS_ERR_TOO_LARGE: input exceeds the supported size";
+    case PS_ERR_OUT_OF_MEMORY: return "PS_ERR_OUT_OF_MEMORY: scratch allocation failed";
+    case PS_ERR_HIP: return "PS_ERR_HIP: HIP runtime error";
+    case PS_ERR_UNSUPPORTED: return "PS_ERR_UNSUPPORTED: unsupported option";
+    }
+    return "unknown ps_status";
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Shared device-side definitions of the powersort HIP library (gfx950).
+//
+// Keys of every supported type are compared as unsigned "order keys": a
+// bijective bit map under which unsigned integer order is the key order
+// (two's-complement integers: flip the sign bit; binary32: IEEE totalOrder).
+// Kernels map keys on load and map them back on store, so buffers always hold
+// the caller's bit patterns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+enum KeyType : int { KT_I32 = 0, KT_U32 = 1, KT_I64 = 2, KT_U64 = 3, KT_F32 = 4 };
+
+template <int KT> struct Key;
+template <> struct Key<KT_I32> {
+    using raw = uint32_t;
+    using ukey = uint32_t;
+    static __device__ __forceinline__ ukey ord(raw x) { return x ^ 0x80000000u; }
+    static __device__ __forceinline__ raw unord(ukey u) { return u ^ 0x80000000u; }
+};
+template <> struct Key<KT_U32> {
+    using raw = uint32_t;
+    using ukey = uint32_t;
+    static __device__ __forceinline__ ukey ord(raw x) { return x; }
+    static __device__ __forceinline__ raw unord(ukey u) { return u; }
+};
+template <> struct Key<KT_I64> {
+    using raw = uint64_t;
+    using ukey = uint64_t;
+    static __device__ __forceinline__ ukey ord(raw x) { return x ^ 0x8000000000000000ull; }
+    static __device__ __forceinline__ raw unord(ukey u) { return u ^ 0x8000000000000000ull; }
+};
+template <> struct Key<KT_U64> {
+    using raw = uint64_t;
+    using ukey = uint64_t;
+    static __device__ __forceinline__ ukey ord(raw x) { return x; }
+    static __device__ __forceinline__ raw unord(ukey u) { return u; }
+};
+// binary32 totalOrder: negative values have all bits flipped, non-negative
+// values get the sign bit set.
+template <> struct Key<KT_F32> {
+    using raw = uint32_t;
+    using ukey = uint32_t;
+    static __device__ __forceinline__ ukey ord(raw x) {
+        return (x & 0x80000000u) ? ~x : (x | 0x80000000u);
+    }
+    static __device__ __forceinline__ raw unord(ukey u) {
+        return (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    }
+};
+
+// ------------------------------------------------------------- tile shapes
+
+constexpr int kThreads = 256;       // threads per workgroup (4 wave64s)
+constexpr int kWaves = kThreads / 64;
+
+// Run partition: tiles of kPartTile positions, plus a halo of w+1 keys.
+constexpr int kPartItems = 16;
+constexpr int kPartTile = kThreads * kPartItems;  // 4096
+constexpr int kMaxMinRun = 64;                    // largest supported w
+constexpr int kScanGroup = 128;                   // tables composed per group (LDS: 128*(w+1)*5 B)
+
+// Fused subtrees: every maximal subtree of at most kFuse elements is formed
+// and merged entirely in LDS by one workgroup.
+constexpr int kFuseItems = 16;
+constexpr int kFuse = kThreads * kFuseItems;      // 4096
+constexpr int kFuseMaxNodes = kFuse / 2;          // internal nodes per subtree (w = 1 worst case)
+
+// Global merge passes: merge-path tiles of kMergeTile outputs.
+constexpr int kMergeItems = 16;
+constexpr int kMergeTile = kThreads * kMergeItems;  // 4096
+
+// Copy/reverse of leaves longer than kFuse.
+constexpr int kLeafTile = 16384;
+
+constexpr int kMaxPower = 32;  // powers are at most floor(lg n) + 1 <= 32 for n < 2^31
+
+// Per-call limits.
+constexpr uint64_t kMaxSegment = (1ull << 31) - 1;
+constexpr uint64_t kMaxTotal = 0xFFFFFFFFull;
+
+__device__ __forceinline__ int clz32(uint32_t x) { return __clz(x); }
+
+}  // namespace ps

@@ -1,0 +1,100 @@
+// Internal interfaces between the translation units of the library.
+#pragma once
+#include "common.hpp"
+
+namespace ps {
+
+struct Counters {
+    uint32_t r;            // number of leaves
+    uint32_t nunits;       // fused subtrees
+    uint32_t nbigleaf;     // leaves longer than kFuse
+    uint32_t error;
+    uint32_t pcount[kMaxPower + 1];  // big nodes per power
+    uint32_t pfill[kMaxPower + 1];
+    uint32_t pbase[kMaxPower + 1];
+    uint32_t ptiles[kMaxPower + 1];  // merge tiles per power; [0] = big-leaf tiles
+};
+
+struct Mask2 {
+    uint64_t a, b;
+};
+
+struct TreeLists {
+    uint32_t* unit_a;
+    uint32_t* unit_b;
+    uint8_t* unit_par;
+    uint32_t* bigleaf;
+    uint8_t* bigleaf_mode;
+    uint32_t* bucket;       // big nodes grouped by power
+    uint32_t* bucket_tile;  // first merge tile of each bucket entry (within its pass)
+    uint32_t* leaf_tile;    // first copy tile of each big leaf
+};
+
+struct TreeArgs {
+    const void* keys;
+    const uint64_t* offsets;
+    uint32_t nseg;
+    uint32_t rmax;
+    uint32_t* starts;
+    Counters* cnt;
+    uint64_t* Q;
+    uint8_t* P;
+    uint8_t* leaf_depth;
+    uint8_t* node_depth;
+    Mask2* aggF;
+    Mask2* aggB;
+    uint64_t* inF;
+    uint64_t* inB;
+    uint64_t* mc;
+    uint32_t* Lf;
+    uint32_t* Rt;
+    TreeLists lists;
+};
+
+struct PartitionArgs {
+    const void* keys;
+    uint32_t N;
+    const uint64_t* offsets;
+    uint32_t nseg;
+    uint32_t w;
+    uint8_t* code[4];
+    uint32_t* cnt[4];
+    uint8_t* entry[4];
+    uint32_t* offs[4];
+    uint32_t ntab[4];
+    int levels;
+    uint32_t* starts;
+    uint32_t* r_dev;
+    uint32_t rmax;  // capacity of the leaf arrays
+};
+
+struct MoveArgs {
+    void* keys[2];
+    uint32_t* pay[2];
+    const uint32_t* starts;
+    const uint8_t* P;
+    const uint32_t* Lf;
+    const uint32_t* Rt;
+    const uint8_t* node_depth;
+    const Counters* cnt;
+    const uint32_t* unit_a;
+    const uint32_t* unit_b;
+    const uint8_t* unit_par;
+    const uint32_t* bigleaf;
+    const uint8_t* bigleaf_mode;
+    const uint32_t* bucket;
+    const uint32_t* bucket_tile;
+    const uint32_t* leaf_tile;
+};
+
+enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace = 3 };
+
+hipError_t launch_partition(int kt, const PartitionArgs& a, hipStream_t st);
+hipError_t launch_init(Counters* cnt, uint64_t* mc, uint32_t nseg, hipStream_t st);
+hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st);
+hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st);
+hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st);
+hipError_t launch_moves(int kt, bool hp, const MoveArgs& a, uint32_t pmax, uint32_t grid_leaf, uint32_t grid_fuse,
+                        uint32_t grid_merge, hipStream_t st);
+
+}  // namespace ps

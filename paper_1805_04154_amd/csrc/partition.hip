@@ -1,0 +1,389 @@
+// Run detection and the leaf partition (Sec. 2 run convention; Alg. PowerSort
+// with the minimum-run extension of App. B.4).
+//
+// Sequentially, the leaves are the orbit of position 0 under
+//     J(s) = min(segEnd(s), max(runEnd(s), s + w)),
+// where runEnd(s) is the end of the natural run that starts at s (weakly
+// increasing, or strictly decreasing) on the ORIGINAL data: a merge only
+// touches positions left of the next run start and a min-run extension only
+// positions inside its own leaf, so the partition never depends on data the
+// algorithm has already moved.
+//
+// In parallel: tile t = [T0, T1) of kPartTile positions is entered by the
+// chain at one of w+1 candidate points: T0 + c for c < w, or the end X0 of the
+// natural run that crosses T0 (the only way the chain can jump further).  For
+// each candidate the tile records the candidate through which the chain
+// leaves (an "exit code" into the next tile) and how many leaf starts it
+// visits.  These small tables compose associatively; a hierarchical scan over
+// them yields each tile's true entry, and a second pass over the tile emits
+// the leaf starts.
+#include "common.hpp"
+#include "block.hpp"
+#include "internal.hpp"
+
+namespace ps {
+
+constexpr int kPairItems = 17;                     // pairs per thread in the window scan
+constexpr int kPairCap = kThreads * kPairItems;    // 4352 >= kPartTile + kMaxMinRun + 2
+constexpr uint32_t kFar = 0xFFFFFFFEu;             // a position beyond the tile's window (!= kInf)
+constexpr uint16_t kExitBit = 0x8000u;
+
+enum : uint8_t { kAsc = 0, kDesc = 1, kBreak = 2, kUnknown = 3 };
+
+template <int KT>
+struct PartShared {
+    using U = typename Key<KT>::ukey;
+    union {
+        U keys[kPairCap + 1];                 // window keys, position T0-1+k at index k
+        struct {
+            uint16_t nx[2][kPartTile];        // successor (or exit) per tile position
+            uint16_t ct[2][kPartTile];        // leaf starts up to the exit
+        } pj;
+        struct {
+            uint16_t nx[2][kPartTile];
+            uint8_t mk[kPartTile];            // chain-point marks
+        } em;
+    } u;
+    uint8_t pt[kPairCap];                     // pair type of pair (T0-1+k, T0+k)
+    uint32_t sh[2 * kWaves];
+    uint32_t gfirst;
+    uint32_t x0;                              // end of the run crossing T0 (kFar / kInf)
+    int flag;
+};
+
+// Computes, for every position s of tile [T0, T1), the encoded successor
+// J(s): a tile-local index if J(s) < T1, else kExitBit | exit code.  The
+// result is left in sm.u.pj.nx[0] (aliased by sm.u.em.nx[0]); sm.x0 receives
+// the end of the natural run crossing T0 (kInf if none, kFar if beyond the
+// window).
+template <int KT>
+__device__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
+                                const uint64_t* __restrict__ offsets, uint32_t nseg, uint32_t w,
+                                uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
+    using K = Key<KT>;
+    using U = typename K::ukey;
+    const int tid = threadIdx.x;
+    // Window: positions [T0-1, WE) as indices [0, NPW); pair k = (T0-1+k, T0+k).
+    const uint32_t WE = (uint32_t)min<uint64_t>((uint64_t)N, (uint64_t)T1 + w + 1);
+    const uint32_t NPW = WE - T0 + 1;  // number of positions in the window = pairs
+
+    for (uint32_t k = tid; k < NPW; k += kThreads) {
+        if (k == 0 && T0 == 0) continue;
+        sm.u.keys[k] = K::ord(keys[T0 - 1 + k]);
+    }
+    if (tid == 0) {
+        // First offset index whose value exceeds T0-1 (segment starts in the window).
+        uint32_t lo = 0, hi = nseg + 1;
+        const uint64_t v = (uint64_t)T0;  // offsets > T0-1  <=>  offsets >= T0
+        while (lo < hi) {
+            uint32_t m = (lo + hi) >> 1;
+            if (offsets[m] < v) lo = m + 1; else hi = m;
+        }
+        sm.gfirst = lo;
+    }
+    __syncthreads();
+    for (uint32_t k = tid; k < NPW; k += kThreads) {
+        uint8_t t;
+        if (k == 0 && T0 == 0) t = kBreak;               // nothing left of position 0
+        else if (k + 1 < NPW) t = (sm.u.keys[k + 1] < sm.u.keys[k]) ? kDesc : kAsc;
+        else t = (WE == N) ? kBreak : kUnknown;         // pair (WE-1, WE)
+        sm.pt[k] = t;
+    }
+    __syncthreads();
+    // A segment start o in (T0-1, WE] breaks pair o-1: runs never cross it.
+    for (uint32_t g = sm.gfirst + tid; g <= nseg; g += kThreads) {
+        const uint64_t o = offsets[g];
+        if (o > (uint64_t)WE) break;
+        if (o >= 1 && o >= (uint64_t)T0) sm.pt[(uint32_t)(o - T0)] = kBreak;
+    }
+    __syncthreads();
+
+    // Per thread: pairs k = tid*kPairItems + i.
+    uint8_t tp[kPairItems];
+    uint32_t cpos_min = kInf, bpos_min = kInf;
+#pragma unroll
+    for (int i = 0; i < kPairItems; ++i) {
+        const uint32_t k = tid * kPairItems + i;
+        tp[i] = (k < NPW) ? sm.pt[k] : kUnknown;
+        const bool chg = (k < NPW) && k > 0 && tp[i] != sm.pt[k - 1];
+        if (chg) cpos_min = min(cpos_min, k);
+        if (k < NPW && tp[i] == kBreak) bpos_min = min(bpos_min, k);
+    }
+    const uint32_t cex = block_excl_suffix_min(cpos_min, sm.sh);
+    const uint32_t bex = block_excl_suffix_min(bpos_min, sm.sh + kWaves);
+    // Right-to-left: nextc[k] = first k' > k where the pair type changes,
+    // nextb[k] = first k' >= k that is a break.
+    uint32_t runc = cex, runb = bex;
+    uint32_t nextc[kPairItems], nextb[kPairItems];
+#pragma unroll
+    for (int i = kPairItems - 1; i >= 0; --i) {
+        const uint32_t k = tid * kPairItems + i;
+        nextc[i] = runc;
+        if (k < NPW && k > 0 && tp[i] != sm.pt[k - 1]) runc = k;
+        if (k < NPW && tp[i] == kBreak) runb = k;
+        nextb[i] = runb;
+    }
+    __syncthreads();  // the key window is dead from here on (aliased by nx)
+
+#pragma unroll
+    for (int i = 0; i < kPairItems; ++i) {
+        const uint32_t k = tid * kPairItems + i;
+        if (k >= NPW) continue;
+        // End of the run containing pair k, as a position (kFar if unknown).
+        uint32_t ne;
+        if (tp[i] == kBreak) {
+            ne = T0 + k;  // the run starting at T0-1+k is that single element
+        } else if (tp[i] == kUnknown) {
+            ne = kFar;
+        } else {
+            const uint32_t kc = nextc[i];
+            ne = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : (T0 + kc);
+        }
+        if (k == 0) {
+            // Run crossing T0: only a real (non-break) pair (T0-1, T0) crosses.
+            sm.x0 = (tp[i] == kBreak) ? kInf : ne;
+            continue;
+        }
+        const uint32_t s = T0 - 1 + k;
+        if (s >= T1) continue;
+        const uint32_t seg_end = (nextb[i] == kInf) ? kFar : (T0 + nextb[i]);
+        uint32_t J;
+        if (ne == kFar) J = kFar;
+        else if (ne - s >= w) J = ne;
+        else J = min(seg_end, s + w);
+        uint16_t enc;
+        if (J < T1) enc = (uint16_t)(J - T0);
+        else enc = kExitBit | (uint16_t)((J != kFar && J - T1 < w) ? (J - T1) : w);
+        sm.u.pj.nx[0][s - T0] = enc;
+    }
+    __syncthreads();
+}
+
+// Pass 1: per-tile exit tables.  For candidate c (c < w: position T0+c;
+// c == w: the end of the run crossing T0), tcode[t][c] is the exit code into
+// tile t+1 and tcnt[t][c] the number of leaf starts visited inside tile t.
+template <int KT>
+__global__ __launch_bounds__(kThreads) void part_tables_kernel(
+    const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
+    uint32_t nseg, uint32_t w, uint8_t* __restrict__ tcode, uint32_t* __restrict__ tcnt) {
+    __shared__ PartShared<KT> sm;
+    const uint32_t T0 = blockIdx.x * kPartTile;
+    const uint32_t T1 = min(N, T0 + kPartTile);
+    const uint32_t len = T1 - T0;
+    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
+
+    // Pointer jumping to the exits, counting visited positions.
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.pj.ct[0][i] = 1;
+    __syncthreads();
+    int cur = 0;
+    for (int round = 0; round < 16; ++round) {
+        int any = 0;
+        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
+            const uint16_t a = sm.u.pj.nx[cur][i];
+            uint16_t na = a, nc = sm.u.pj.ct[cur][i];
+            if (!(a & kExitBit)) {
+                na = sm.u.pj.nx[cur][a];
+                nc = (uint16_t)(nc + sm.u.pj.ct[cur][a]);
+                any |= !(na & kExitBit);
+            }
+            sm.u.pj.nx[cur ^ 1][i] = na;
+            sm.u.pj.ct[cur ^ 1][i] = nc;
+        }
+        cur ^= 1;
+        if (!__syncthreads_or(any)) break;
+    }
+
+    const uint32_t W1 = w + 1;
+    for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
+        uint32_t pos;
+        bool valid = true;
+        if (c < w) {
+            pos = T0 + c;
+        } else {
+            pos = sm.x0;
+            if (pos == kInf || (pos != kFar && pos < T0 + w)) valid = false;  // never entered this way
+        }
+        uint8_t code;
+        uint32_t cnt;
+        if (!valid) {
+            pos = T0;  // filler: any well-defined entry
+        }
+        if (pos == kFar || pos >= T1) {
+            code = (uint8_t)((pos != kFar && pos - T1 < w) ? (pos - T1) : w);
+            cnt = 0;
+        } else {
+            const uint16_t e = sm.u.pj.nx[cur][pos - T0];
+            code = (uint8_t)(e & 0xFF);
+            cnt = sm.u.pj.ct[cur][pos - T0];
+        }
+        tcode[(size_t)blockIdx.x * W1 + c] = code;
+        tcnt[(size_t)blockIdx.x * W1 + c] = cnt;
+    }
+}
+
+// Up-sweep: compose groups of kScanGroup consecutive tables into one.
+// Table k maps an entry code to (exit code, count); composing k then k+1
+// gives c -> (E_{k+1}[E_k[c]], C_k[c] + C_{k+1}[E_k[c]]).
+__global__ __launch_bounds__(kThreads) void compose_up_kernel(const uint8_t* __restrict__ code_in,
+                                                               const uint32_t* __restrict__ cnt_in,
+                                                               uint32_t ntab, uint32_t W1,
+                                                               uint8_t* __restrict__ code_out,
+                                                               uint32_t* __restrict__ cnt_out) {
+    extern __shared__ unsigned char dyn[];
+    uint32_t* scnt = reinterpret_cast<uint32_t*>(dyn);                        // [kScanGroup][W1]
+    uint8_t* scode = reinterpret_cast<uint8_t*>(scnt + kScanGroup * W1);      // [kScanGroup][W1]
+    const uint32_t base = blockIdx.x * kScanGroup;
+    const uint32_t m = min((uint32_t)kScanGroup, ntab - base);
+    for (uint32_t i = threadIdx.x; i < m * W1; i += kThreads) {
+        scode[i] = code_in[(size_t)base * W1 + i];
+        scnt[i] = cnt_in[(size_t)base * W1 + i];
+    }
+    __syncthreads();
+    // In-place tree: at stride s, table i (i % 2s == 0) absorbs table i+s.
+    for (uint32_t s = 1; s < m; s <<= 1) {
+        const uint32_t npairs = (m + 2 * s - 1) / (2 * s);
+        for (uint32_t x = threadIdx.x; x < npairs * W1; x += kThreads) {
+            const uint32_t pr = x / W1, c = x % W1;
+            const uint32_t a = pr * 2 * s, b = a + s;
+            if (b < m) {
+                const uint32_t e = scode[a * W1 + c];
+                scnt[a * W1 + c] += scnt[b * W1 + e];
+                scode[a * W1 + c] = scode[b * W1 + e];
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
+        code_out[(size_t)blockIdx.x * W1 + c] = scode[c];
+        cnt_out[(size_t)blockIdx.x * W1 + c] = scnt[c];
+    }
+}
+
+// Down-sweep: given each group's entry code and leaf offset, walk its tables
+// in order and record every table's entry code and offset.  At the top level
+// (entry_in == nullptr) the single group is entered at position 0 with
+// offset 0; at level 0 (final != nullptr) the last group also writes r and
+// starts[r] = N.
+__global__ __launch_bounds__(kThreads) void compose_down_kernel(
+    const uint8_t* __restrict__ code_in, const uint32_t* __restrict__ cnt_in, uint32_t ntab, uint32_t W1,
+    const uint8_t* __restrict__ entry_in, const uint32_t* __restrict__ off_in, uint8_t* __restrict__ entry_out,
+    uint32_t* __restrict__ off_out, uint32_t* __restrict__ r_out, uint32_t* __restrict__ starts, uint32_t N,
+    uint32_t rcap) {
+    extern __shared__ unsigned char dyn[];
+    uint32_t* scnt = reinterpret_cast<uint32_t*>(dyn);
+    uint8_t* scode = reinterpret_cast<uint8_t*>(scnt + kScanGroup * W1);
+    const uint32_t base = blockIdx.x * kScanGroup;
+    const uint32_t m = min((uint32_t)kScanGroup, ntab - base);
+    for (uint32_t i = threadIdx.x; i < m * W1; i += kThreads) {
+        scode[i] = code_in[(size_t)base * W1 + i];
+        scnt[i] = cnt_in[(size_t)base * W1 + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t e = entry_in ? entry_in[blockIdx.x] : 0;
+        uint32_t off = off_in ? off_in[blockIdx.x] : 0;
+        for (uint32_t k = 0; k < m; ++k) {
+            entry_out[base + k] = (uint8_t)e;
+            off_out[base + k] = off;
+            off += scnt[k * W1 + e];
+            e = scode[k * W1 + e];
+        }
+        if (r_out && base + m == ntab) {
+            off = min(off, rcap);  // never past the leaf arrays
+            *r_out = off;
+            starts[off] = N;
+        }
+    }
+}
+
+// Pass 2: emit the leaf starts of each tile, entered at its true entry code.
+// The chain points are marked by doubling: after round k the first 2^k
+// points from the entry are marked and nx holds J^(2^k).
+template <int KT>
+__global__ __launch_bounds__(kThreads) void part_emit_kernel(
+    const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
+    uint32_t nseg, uint32_t w, const uint8_t* __restrict__ entry, const uint32_t* __restrict__ offs,
+    uint32_t* __restrict__ starts, uint32_t rcap) {
+    __shared__ PartShared<KT> sm;
+    const uint32_t T0 = blockIdx.x * kPartTile;
+    const uint32_t T1 = min(N, T0 + kPartTile);
+    const uint32_t len = T1 - T0;
+    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
+    const uint32_t e = entry[blockIdx.x];
+    uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
+    if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.em.mk[i] = (i == pos - T0);
+    __syncthreads();
+    int cur = 0;
+    for (int round = 0; round < 16; ++round) {
+        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
+            const uint16_t a = sm.u.em.nx[cur][i];
+            if (sm.u.em.mk[i] && !(a & kExitBit)) sm.u.em.mk[a] = 1;
+        }
+        __syncthreads();
+        int any = 0;
+        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
+            const uint16_t a = sm.u.em.nx[cur][i];
+            uint16_t na = a;
+            if (!(a & kExitBit)) {
+                na = sm.u.em.nx[cur][a];
+                any |= !(na & kExitBit);
+            }
+            sm.u.em.nx[cur ^ 1][i] = na;
+        }
+        cur ^= 1;
+        // Once J^(2^(round+1)) leaves the tile from every position, the chain
+        // from the entry has at most 2^(round+1) points, all marked by now.
+        if (!__syncthreads_or(any)) break;
+    }
+    // Compact the marks in position order.
+    uint32_t cnt = 0;
+    const uint32_t i0 = threadIdx.x * kPartItems;
+#pragma unroll
+    for (int i = 0; i < kPartItems; ++i)
+        if (i0 + i < len && sm.u.em.mk[i0 + i]) ++cnt;
+    uint32_t rank = block_excl_sum(cnt, sm.sh, nullptr) + offs[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kPartItems; ++i)
+        if (i0 + i < len && sm.u.em.mk[i0 + i]) {
+            if (rank < rcap) starts[rank] = T0 + i0 + i;
+            ++rank;
+        }
+}
+
+// ------------------------------------------------------------- host launch
+
+template <int KT>
+hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
+    using raw = typename Key<KT>::raw;
+    const uint32_t nT = a.ntab[0];
+    const uint32_t W1 = a.w + 1;
+    hipLaunchKernelGGL(part_tables_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N,
+                       a.offsets, a.nseg, a.w, a.code[0], a.cnt[0]);
+    const size_t lds = (size_t)kScanGroup * W1 * 5;
+    for (int l = 0; l + 1 < a.levels; ++l)
+        hipLaunchKernelGGL(compose_up_kernel, dim3(a.ntab[l + 1]), dim3(kThreads), lds, st, a.code[l], a.cnt[l],
+                           a.ntab[l], W1, a.code[l + 1], a.cnt[l + 1]);
+    for (int l = a.levels - 1; l >= 0; --l) {
+        const bool top = (l == a.levels - 1);
+        hipLaunchKernelGGL(compose_down_kernel, dim3(top ? 1 : a.ntab[l + 1]), dim3(kThreads), lds, st, a.code[l],
+                           a.cnt[l], a.ntab[l], W1, top ? nullptr : a.entry[l + 1], top ? nullptr : a.offs[l + 1],
+                           a.entry[l], a.offs[l], l == 0 ? a.r_dev : nullptr, a.starts, a.N, a.rmax);
+    }
+    hipLaunchKernelGGL(part_emit_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N, a.offsets,
+                       a.nseg, a.w, a.entry[0], a.offs[0], a.starts, a.rmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition(int kt, const PartitionArgs& a, hipStream_t st) {
+    switch (kt) {
+    case KT_I32: return launch_partition_t<KT_I32>(a, st);
+    case KT_U32: return launch_partition_t<KT_U32>(a, st);
+    case KT_I64: return launch_partition_t<KT_I64>(a, st);
+    case KT_U64: return launch_partition_t<KT_U64>(a, st);
+    case KT_F32: return launch_partition_t<KT_F32>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ps

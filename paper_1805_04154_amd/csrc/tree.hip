@@ -1,0 +1,502 @@
+// Node powers and the merge tree.
+//
+// Leaves i = 0..r-1 (after the min-run extension) have starts S_i; boundary j
+// (1 <= j < r) separates leaves j-1 and j.  Per Def. "Node Power" the power of
+// boundary j is the first bit in which the binary fractions of the two run
+// midpoints differ.  With q_i = floor((2 (S_i - off) + L_i) 2^32 / (2 n)), the
+// 32-bit fixed-point midpoint of leaf i in its segment (origin off, length n),
+// P_j = clz32(q_{j-1} xor q_j) + 1: the fixed point agrees with the exact
+// definition because midpoints of adjacent leaves differ by at least 1/n > 2^-31.
+// Each leaf stores Q_i = (segment << 32) | q_i, strictly increasing over the
+// whole batch; a boundary between segments gets power 0.
+//
+// By Cor. "Cartesian tree" the merge tree is the min-oriented Cartesian tree
+// of the powers.  Two facts make it parallel:
+//   * depth: the left ancestors of leaf i are the strict suffix minima of
+//     P_1..P_i and the right ones the strict prefix minima of P_{i+1}..P_{r-1};
+//     their powers are distinct, so each side is a bit set over powers, and
+//     "drop every power >= p, add p" composes associatively as a pair of
+//     masks (A, B): G -> (G & A) | B.  Two scans give every depth, the buffer
+//     parity of every leaf and node, and M = sum_i depth_i L_i (Sec. 2.3).
+//   * ranges: node j of power p merges exactly the leaves whose q share their
+//     top p-1 bits with q_j (the level-(p-1) dyadic cell of Method 2'), a
+//     contiguous block of the sorted Q array found by galloping search.
+#include "common.hpp"
+#include "block.hpp"
+#include "internal.hpp"
+
+namespace ps {
+
+constexpr int kMaskItems = 16;
+constexpr int kMaskBlock = kThreads * kMaskItems;  // 4096 boundaries per block
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ Mask2 mcompose(Mask2 x, Mask2 y) {  // x first, then y
+    return Mask2{x.a & y.a, (x.b & y.a) | y.b};
+}
+__device__ __forceinline__ Mask2 midentity() { return Mask2{~0ull, 0ull}; }
+__device__ __forceinline__ Mask2 mof(uint32_t p) {
+    return Mask2{p ? ((1ull << p) - 1ull) : 0ull, 1ull << p};
+}
+__device__ __forceinline__ Mask2 mshfl_up(Mask2 v, int d) {
+    return Mask2{__shfl_up(v.a, d), __shfl_up(v.b, d)};
+}
+__device__ __forceinline__ Mask2 mshfl_down(Mask2 v, int d) {
+    return Mask2{__shfl_down(v.a, d), __shfl_down(v.b, d)};
+}
+
+// Exclusive forward (left-to-right) scan of thread aggregates over the block.
+__device__ Mask2 block_excl_fwd(Mask2 v, Mask2* sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Mask2 incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        Mask2 o = mshfl_up(incl, d);
+        if (lane >= d) incl = mcompose(o, incl);
+    }
+    Mask2 ex = mshfl_up(incl, 1);
+    if (lane == 0) ex = midentity();
+    if (lane == 63) sh[wid] = incl;
+    __syncthreads();
+    Mask2 pre = midentity();
+    for (int w2 = 0; w2 < wid; ++w2) pre = mcompose(pre, sh[w2]);
+    __syncthreads();
+    return mcompose(pre, ex);
+}
+
+// Exclusive backward (right-to-left) scan: composition of all threads > tid,
+// rightmost first.
+__device__ Mask2 block_excl_bwd(Mask2 v, Mask2* sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Mask2 incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        Mask2 o = mshfl_down(incl, d);
+        if (lane + d < 64) incl = mcompose(o, incl);
+    }
+    Mask2 ex = mshfl_down(incl, 1);
+    if (lane == 63) ex = midentity();
+    if (lane == 0) sh[wid] = incl;
+    __syncthreads();
+    Mask2 suf = midentity();
+    for (int w2 = kWaves - 1; w2 > wid; --w2) suf = mcompose(suf, sh[w2]);
+    __syncthreads();
+    return mcompose(suf, ex);
+}
+
+__device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ offsets, uint32_t nseg, uint64_t s) {
+    // largest g with offsets[g] <= s (the non-empty segment holding s)
+    uint32_t lo = 0, hi = nseg + 1;
+    while (lo < hi) {
+        uint32_t m = (lo + hi) >> 1;
+        if (offsets[m] <= s) lo = m + 1; else hi = m;
+    }
+    return lo - 1;
+}
+
+__global__ __launch_bounds__(kThreads) void init_counters_kernel(Counters* c, uint64_t* mc, uint32_t nseg) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(c);
+    const uint32_t nw = sizeof(Counters) / 4;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nw; i += gridDim.x * kThreads) w[i] = 0;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nseg; i += gridDim.x * kThreads) mc[i] = 0;
+}
+
+// Fixed-point midpoints Q_i for all leaves.
+__global__ __launch_bounds__(kThreads) void leaf_q_kernel(const uint32_t* __restrict__ starts,
+                                                           const uint32_t* __restrict__ r_dev,
+                                                           const uint64_t* __restrict__ offsets, uint32_t nseg,
+                                                           uint64_t* __restrict__ Q) {
+    const uint32_t r = *r_dev;
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < r; i += gridDim.x * kThreads) {
+        const uint32_t s = starts[i], e = starts[i + 1];
+        const uint32_t g = seg_of(offsets, nseg, s);
+        const uint64_t off = offsets[g], ng = offsets[g + 1] - off;
+        const uint64_t twice_mid = (uint64_t)(s - off) + (uint64_t)(e - off);  // 2 (S - off) + L < 2 n
+        const uint64_t q = (twice_mid << 32) / (2 * ng);
+        Q[i] = ((uint64_t)g << 32) | q;
+    }
+}
+
+__device__ __forceinline__ uint32_t power_at(const uint64_t* __restrict__ Q, uint32_t j) {
+    if (j == 0) return 0;
+    const uint64_t x = Q[j - 1] ^ Q[j];
+    if (x >> 32) return 0;  // the two leaves lie in different segments
+    return (uint32_t)__clz((uint32_t)x) + 1;
+}
+
+// Mask scan, phase 1: powers P[j] and per-block forward/backward aggregates.
+__global__ __launch_bounds__(kThreads) void mask_reduce_kernel(const uint64_t* __restrict__ Q,
+                                                                const uint32_t* __restrict__ r_dev,
+                                                                uint8_t* __restrict__ P, Mask2* __restrict__ aggF,
+                                                                Mask2* __restrict__ aggB) {
+    __shared__ Mask2 sh[kWaves];
+    const uint32_t r = *r_dev;
+    const uint32_t base = blockIdx.x * kMaskBlock;
+    if (base >= r) return;
+    Mask2 f = midentity(), b = midentity();
+    uint32_t pw[kMaskItems];
+#pragma unroll
+    for (int i = 0; i < kMaskItems; ++i) {
+        const uint32_t j = base + threadIdx.x * kMaskItems + i;
+        pw[i] = (j < r) ? power_at(Q, j) : 0;
+        if (j < r) {
+            P[j] = (uint8_t)pw[i];
+            if (j == r - 1) P[r] = 0;
+            f = mcompose(f, mof(pw[i]));
+        }
+    }
+#pragma unroll
+    for (int i = kMaskItems - 1; i >= 0; --i) {
+        const uint32_t j = base + threadIdx.x * kMaskItems + i;
+        if (j < r) b = mcompose(b, mof(pw[i]));
+    }
+    // Block aggregates: forward = threads left to right; backward = right to left.
+    Mask2 ef = block_excl_fwd(f, sh);
+    Mask2 eb = block_excl_bwd(b, sh);
+    if (threadIdx.x == kThreads - 1) aggF[blockIdx.x] = mcompose(ef, f);
+    if (threadIdx.x == 0) aggB[blockIdx.x] = mcompose(eb, b);
+}
+
+// Mask scan, phase 2 (one block): states entering each block from the left
+// (inF) and from the right (inB).
+__global__ __launch_bounds__(kThreads) void mask_scan_kernel(const Mask2* __restrict__ aggF,
+                                                              const Mask2* __restrict__ aggB,
+                                                              const uint32_t* __restrict__ r_dev,
+                                                              uint64_t* __restrict__ inF, uint64_t* __restrict__ inB) {
+    __shared__ Mask2 sh[kWaves];
+    const uint32_t r = *r_dev;
+    const uint32_t nb = (r + kMaskBlock - 1) / kMaskBlock;
+    const uint32_t per = (nb + kThreads - 1) / kThreads;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    Mask2 f = midentity(), b = midentity();
+    for (uint32_t k = b0; k < b1; ++k) f = mcompose(f, aggF[k]);
+    for (uint32_t k = b1; k > b0; --k) b = mcompose(b, aggB[k - 1]);
+    Mask2 ef = block_excl_fwd(f, sh);
+    Mask2 eb = block_excl_bwd(b, sh);
+    Mask2 cf = ef;
+    for (uint32_t k = b0; k < b1; ++k) {
+        inF[k] = cf.b;
+        cf = mcompose(cf, aggF[k]);
+    }
+    Mask2 cb = eb;
+    for (uint32_t k = b1; k > b0; --k) {
+        inB[k - 1] = cb.b;
+        cb = mcompose(cb, aggB[k - 1]);
+    }
+}
+
+// Mask scan, phase 3: depths of leaves and nodes, and the merge cost
+// M_g = sum over the leaves of segment g of depth * length.
+__global__ __launch_bounds__(kThreads) void mask_apply_kernel(const uint8_t* __restrict__ P,
+                                                               const uint64_t* __restrict__ Q,
+                                                               const uint32_t* __restrict__ starts,
+                                                               const uint32_t* __restrict__ r_dev,
+                                                               const uint64_t* __restrict__ inF,
+                                                               const uint64_t* __restrict__ inB,
+                                                               uint8_t* __restrict__ leaf_depth,
+                                                               uint8_t* __restrict__ node_depth,
+                                                               uint64_t* __restrict__ mc) {
+    __shared__ Mask2 sh[kWaves];
+    const uint32_t r = *r_dev;
+    const uint32_t base = blockIdx.x * kMaskBlock;
+    if (base >= r) return;
+    const uint32_t j0 = base + threadIdx.x * kMaskItems;
+    uint32_t pw[kMaskItems];
+    Mask2 f = midentity(), b = midentity();
+#pragma unroll
+    for (int i = 0; i < kMaskItems; ++i) {
+        const uint32_t j = j0 + i;
+        pw[i] = (j < r) ? P[j] : 0;
+        if (j < r) f = mcompose(f, mof(pw[i]));
+    }
+#pragma unroll
+    for (int i = kMaskItems - 1; i >= 0; --i)
+        if (j0 + i < r) b = mcompose(b, mof(pw[i]));
+    const Mask2 ef = block_excl_fwd(f, sh);
+    const Mask2 eb = block_excl_bwd(b, sh);
+    uint64_t G = (inF[blockIdx.x] & ef.a) | ef.b;
+    uint64_t Gin[kMaskItems];
+#pragma unroll
+    for (int i = 0; i < kMaskItems; ++i) {
+        Gin[i] = G;
+        if (j0 + i < r) {
+            const Mask2 m = mof(pw[i]);
+            G = (G & m.a) | m.b;
+        }
+    }
+    uint64_t H = (inB[blockIdx.x] & eb.a) | eb.b;
+    uint32_t seg_cur = kNone;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = kMaskItems - 1; i >= 0; --i) {
+        const uint32_t j = j0 + i;
+        if (j >= r) continue;
+        const Mask2 m = mof(pw[i]);
+        const uint64_t Hin = H;
+        const uint64_t Gout = (Gin[i] & m.a) | m.b;
+        const uint32_t dl = __popcll(Gout >> 1) + __popcll(Hin >> 1);
+        leaf_depth[j] = (uint8_t)dl;
+        node_depth[j] = (uint8_t)(__popcll((Gin[i] & m.a) >> 1) + __popcll((Hin & m.a) >> 1));
+        H = (H & m.a) | m.b;
+        const uint32_t g = (uint32_t)(Q[j] >> 32);
+        const uint64_t c = (uint64_t)dl * (uint64_t)(starts[j + 1] - starts[j]);
+        if (g != seg_cur) {
+            if (seg_cur != kNone && acc) atomicAdd((unsigned long long*)&mc[seg_cur], (unsigned long long)acc);
+            seg_cur = g;
+            acc = 0;
+        }
+        acc += c;
+    }
+    // Flush the thread's last partial sum; a wave whose lanes all hold the
+    // same segment adds once.
+    const int lane = threadIdx.x & 63;
+    const uint64_t act = __ballot(seg_cur != kNone);
+    const int leader = act ? (__ffsll((unsigned long long)act) - 1) : 0;
+    const uint32_t seg0 = __shfl(seg_cur, leader);
+    const bool uniform = __all(seg_cur == kNone || seg_cur == seg0);
+    if (uniform) {
+        uint64_t s = acc;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d);
+        if (lane == 0 && act && s) atomicAdd((unsigned long long*)&mc[seg0], (unsigned long long)s);
+    } else if (seg_cur != kNone && acc) {
+        atomicAdd((unsigned long long*)&mc[seg_cur], (unsigned long long)acc);
+    }
+}
+
+// Leaf range [Lf, Rt) of every node: the leaves whose Q agree with Q_j on
+// the segment and the top P_j - 1 fraction bits.
+__global__ __launch_bounds__(kThreads) void node_range_kernel(const uint64_t* __restrict__ Q,
+                                                               const uint8_t* __restrict__ P,
+                                                               const uint32_t* __restrict__ r_dev,
+                                                               uint32_t* __restrict__ Lf, uint32_t* __restrict__ Rt) {
+    const uint32_t r = *r_dev;
+    for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < r; j += gridDim.x * kThreads) {
+        const uint32_t p = P[j];
+        if (j == 0 || p == 0) continue;
+        const uint32_t sh = 33 - p;
+        const uint64_t key = Q[j] >> sh;
+        // Left: first match in [0, j-1]; Q[j-1] matches.
+        int64_t hi = (int64_t)j - 1;
+        int64_t d = 1;
+        while (hi - d >= 0 && (Q[hi - d] >> sh) == key) d <<= 1;
+        int64_t lo = max<int64_t>(0, hi - d + 1), up = hi - (d >> 1);
+        while (lo < up) {
+            const int64_t m = (lo + up) >> 1;
+            if ((Q[m] >> sh) == key) up = m; else lo = m + 1;
+        }
+        Lf[j] = (uint32_t)lo;
+        // Right: last match in [j, r-1]; Q[j] matches.
+        d = 1;
+        while ((int64_t)j + d < (int64_t)r && (Q[j + d] >> sh) == key) d <<= 1;
+        lo = (int64_t)j + (d >> 1);
+        up = min<int64_t>((int64_t)r - 1, (int64_t)j + d - 1);
+        while (lo < up) {
+            const int64_t m = (lo + up + 1) >> 1;
+            if ((Q[m] >> sh) == key) lo = m; else up = m - 1;
+        }
+        Rt[j] = (uint32_t)lo + 1;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(pred);
+    if (!m) return kNone;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)) : kNone;
+}
+
+// Classify leaves and nodes: fused-subtree roots (maximal subtrees of at most
+// kFuse elements), leaves longer than kFuse, and big nodes (counted per power).
+template <int KT>
+__global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<KT>::raw* __restrict__ keys,
+                                                             const uint32_t* __restrict__ starts,
+                                                             const uint8_t* __restrict__ P,
+                                                             const uint32_t* __restrict__ Lf,
+                                                             const uint32_t* __restrict__ Rt,
+                                                             const uint8_t* __restrict__ leaf_depth,
+                                                             const uint8_t* __restrict__ node_depth,
+                                                             Counters* __restrict__ cnt, TreeLists L) {
+    using K = Key<KT>;
+    const uint32_t r = cnt->r;
+    auto size_of = [&](uint32_t j) -> uint32_t { return starts[Rt[j]] - starts[Lf[j]]; };
+    for (uint32_t i0 = blockIdx.x * kThreads; i0 < r; i0 += gridDim.x * kThreads) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool valid = i < r;
+        // ---- node i (boundary between leaves i-1 and i)
+        bool unit_node = false, big_node = false;
+        uint32_t nlf = 0, nrt = 0;
+        if (valid && i >= 1 && P[i] >= 1) {
+            nlf = Lf[i];
+            nrt = Rt[i];
+            const uint32_t sz = starts[nrt] - starts[nlf];
+            if (sz > (uint32_t)kFuse) {
+                big_node = true;
+            } else {
+                const uint32_t pl = P[nlf], pr = P[nrt];
+                const uint32_t par = pl > pr ? nlf : (pr > pl ? nrt : kNone);
+                unit_node = (par == kNone) || size_of(par) > (uint32_t)kFuse;
+            }
+        }
+        if (big_node) atomicAdd(&cnt->pcount[P[i]], 1u);
+        uint32_t slot = wave_append(unit_node, &cnt->nunits);
+        if (unit_node) {
+            L.unit_a[slot] = nlf;
+            L.unit_b[slot] = nrt;
+            L.unit_par[slot] = node_depth[i] & 1;
+        }
+        // ---- leaf i
+        bool unit_leaf = false, big_leaf = false;
+        uint8_t mode = kLeafNoop;
+        if (valid) {
+            const uint32_t s = starts[i], len = starts[i + 1] - s;
+            const uint32_t pl = P[i], pr = P[i + 1];
+            const uint32_t par = pl > pr ? i : (pr > pl ? i + 1 : kNone);
+            if (len > (uint32_t)kFuse) {
+                big_leaf = true;
+                const bool desc = K::ord(keys[s + 1]) < K::ord(keys[s]);
+                const bool odd = leaf_depth[i] & 1;
+                mode = desc ? (odd ? kLeafRevCopy : kLeafRevInPlace) : (odd ? kLeafCopy : kLeafNoop);
+            } else {
+                unit_leaf = (par == kNone) || size_of(par) > (uint32_t)kFuse;
+            }
+        }
+        slot = wave_append(unit_leaf, &cnt->nunits);
+        if (unit_leaf) {
+            L.unit_a[slot] = i;
+            L.unit_b[slot] = i + 1;
+            L.unit_par[slot] = leaf_depth[i] & 1;
+        }
+        slot = wave_append(big_leaf, &cnt->nbigleaf);
+        if (big_leaf) {
+            L.bigleaf[slot] = i;
+            L.bigleaf_mode[slot] = mode;
+        }
+    }
+}
+
+__global__ void bucket_base_kernel(Counters* cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int p = 0; p <= kMaxPower; ++p) {
+            cnt->pbase[p] = acc;
+            cnt->pfill[p] = 0;
+            acc += cnt->pcount[p];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint32_t* __restrict__ starts,
+                                                                   const uint8_t* __restrict__ P,
+                                                                   const uint32_t* __restrict__ Lf,
+                                                                   const uint32_t* __restrict__ Rt,
+                                                                   Counters* __restrict__ cnt, TreeLists L) {
+    const uint32_t r = cnt->r;
+    for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < r; j += gridDim.x * kThreads) {
+        const uint32_t p = P[j];
+        if (j == 0 || p == 0) continue;
+        if (starts[Rt[j]] - starts[Lf[j]] <= (uint32_t)kFuse) continue;
+        const uint32_t slot = atomicAdd(&cnt->pfill[p], 1u);
+        L.bucket[cnt->pbase[p] + slot] = j;
+    }
+}
+
+// Tile prefix of each power bucket (block p >= 1) and of the big leaves (block 0).
+__global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __restrict__ starts,
+                                                              const uint32_t* __restrict__ Lf,
+                                                              const uint32_t* __restrict__ Rt,
+                                                              Counters* __restrict__ cnt, TreeLists L) {
+    __shared__ uint32_t sh[kWaves];
+    const uint32_t p = blockIdx.x;
+    const uint32_t n = (p == 0) ? cnt->nbigleaf : cnt->pcount[p];
+    const uint32_t off = (p == 0) ? 0 : cnt->pbase[p];
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += kThreads) {
+        const uint32_t k = c0 + threadIdx.x;
+        uint32_t tiles = 0;
+        if (k < n) {
+            if (p == 0) {
+                const uint32_t i = L.bigleaf[k];
+                const uint32_t len = starts[i + 1] - starts[i];
+                const uint8_t mode = L.bigleaf_mode[k];
+                if (mode == kLeafRevInPlace) tiles = (len / 2 + kLeafTile - 1) / kLeafTile;
+                else if (mode != kLeafNoop) tiles = (len + kLeafTile - 1) / kLeafTile;
+            } else {
+                const uint32_t j = L.bucket[off + k];
+                tiles = (starts[Rt[j]] - starts[Lf[j]] + kMergeTile - 1) / kMergeTile;
+            }
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_sum(tiles, sh, &total);
+        if (k < n) {
+            if (p == 0) L.leaf_tile[k] = carry + ex;
+            else L.bucket_tile[off + k] = carry + ex;
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) cnt->ptiles[p] = carry;
+}
+
+// ------------------------------------------------------------- host launch
+
+static inline uint32_t grid_for(uint64_t items, uint32_t cap) {
+    uint64_t g = (items + kThreads - 1) / kThreads;
+    if (g < 1) g = 1;
+    return (uint32_t)(g < cap ? g : cap);
+}
+
+hipError_t launch_init(Counters* cnt, uint64_t* mc, uint32_t nseg, hipStream_t st) {
+    hipLaunchKernelGGL(init_counters_kernel, dim3(grid_for(nseg + 64, 1024)), dim3(kThreads), 0, st, cnt, mc, nseg);
+    return hipGetLastError();
+}
+
+// Powers, depths and merge cost (everything ps_merge_cost needs).
+hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st) {
+    const uint32_t* r_dev = &a.cnt->r;
+    const uint32_t gl = grid_for(a.rmax, 4096);
+    hipLaunchKernelGGL(leaf_q_kernel, dim3(gl), dim3(kThreads), 0, st, a.starts, r_dev, a.offsets, a.nseg, a.Q);
+    const uint32_t nb = (a.rmax + kMaskBlock - 1) / kMaskBlock;
+    hipLaunchKernelGGL(mask_reduce_kernel, dim3(nb), dim3(kThreads), 0, st, a.Q, r_dev, a.P, a.aggF, a.aggB);
+    hipLaunchKernelGGL(mask_scan_kernel, dim3(1), dim3(kThreads), 0, st, a.aggF, a.aggB, r_dev, a.inF, a.inB);
+    hipLaunchKernelGGL(mask_apply_kernel, dim3(nb), dim3(kThreads), 0, st, a.P, a.Q, a.starts, r_dev, a.inF, a.inB,
+                       a.leaf_depth, a.node_depth, a.mc);
+    return hipGetLastError();
+}
+
+template <int KT>
+static void launch_classify_t(const TreeArgs& a, uint32_t g, hipStream_t st) {
+    using raw = typename Key<KT>::raw;
+    hipLaunchKernelGGL(classify_kernel<KT>, dim3(g), dim3(kThreads), 0, st, (const raw*)a.keys, a.starts, a.P, a.Lf,
+                       a.Rt, a.leaf_depth, a.node_depth, a.cnt, a.lists);
+}
+
+// Node ranges and the work lists of the data-movement phase.
+hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st) {
+    const uint32_t gl = grid_for(a.rmax, 4096);
+    hipLaunchKernelGGL(node_range_kernel, dim3(gl), dim3(kThreads), 0, st, a.Q, a.P, &a.cnt->r, a.Lf, a.Rt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
+    const uint32_t gl = grid_for(a.rmax, 4096);
+    switch (kt) {
+    case KT_I32: launch_classify_t<KT_I32>(a, gl, st); break;
+    case KT_U32: launch_classify_t<KT_U32>(a, gl, st); break;
+    case KT_I64: launch_classify_t<KT_I64>(a, gl, st); break;
+    case KT_U64: launch_classify_t<KT_U64>(a, gl, st); break;
+    case KT_F32: launch_classify_t<KT_F32>(a, gl, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gl), dim3(kThreads), 0, st, a.starts, a.P, a.Lf, a.Rt, a.cnt,
+                       a.lists);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt, a.cnt,
+                       a.lists);
+    return hipGetLastError();
+}
+
+}  // namespace ps
