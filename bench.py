@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X powersort on its headline workload.
+
+One step = one ps_sort of the whole input (run detection, leaf partition,
+node powers, merge tree, leaf formation and every merge) on a fresh copy of
+the input that is already resident in HBM.  Default workload: n = 2^28
+int32 keys with a uint32 index payload, runs of Zipf(1.2) lengths (clipped to
+2^24), keys uniform in [0, 2^20), 10% strictly descending runs.
+
+Prints one JSON line (rank 0) with keys/s, the HBM roofline of the merge-pass
+kernel, the whole-path fraction of the roofline computed from the merge cost,
+and the CPU oracle timed on the host as a reported baseline.
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E
+METRIC = "keys/s and % HBM roofline (2^28 int32+idx); batched/served vs plain; p50/p99"
+WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32")
+
+
+def make_workload(name: str, n: int):
+    from paper_1805_04154_amd import workloads as W
+    if name == "zipf_i32":
+        return W.zipf_runs(n, key_dtype=np.int32)
+    if name == "zipf_u64":
+        return W.zipf_runs(n, key_dtype=np.uint64)
+    if name == "perm_i32":
+        return W.permutation_i32(n)
+    if name == "runs_i32":
+        return W.runs_sqrt_i32(n)
+    raise ValueError(name)
+
+
+def to_dev(a: np.ndarray):
+    import torch
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32)).cuda().view(torch.uint32)
+    if a.dtype == np.uint64:
+        return torch.from_numpy(a.view(np.int64)).cuda().view(torch.uint64)
+    return torch.from_numpy(a).cuda()
+
+
+def cpu_baseline(wl, budget_s: float) -> dict:
+    """The oracle as it stands, single-threaded on a host core, on a prefix
+    of the workload sized to take roughly budget_s seconds."""
+    import oracle
+    n = wl.n
+    m = min(n, 1 << 22)
+    t = time.perf_counter()
+    oracle.powersort(wl.keys[:m], wl.payload[:m], details=False)
+    dt = time.perf_counter() - t
+    # grow the sample while the projected time fits the budget
+    while m < n and dt * 2.2 < budget_s:
+        m = min(n, 2 * m)
+        t = time.perf_counter()
+        oracle.powersort(wl.keys[:m], wl.payload[:m], details=False)
+        dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} of the {n} keys of the same workload (payload = index), one powersort call, "
+                      f"single thread on the host CPU ({os.cpu_count()} logical cores visible), {dt:.2f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--workload", choices=WORKLOADS, default="zipf_i32")
+    ap.add_argument("--min-run", type=int, default=24)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the sort is single-device with no sharding or collectives", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1805_04154_amd import binding
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    binding.load_library()
+    n = 1 << args.log2n
+    t_gen = time.perf_counter()
+    wl = make_workload(args.workload, n)
+    t_gen = time.perf_counter() - t_gen
+    kb = wl.keys.dtype.itemsize
+    rec_bytes = kb + 4  # key + uint32 payload
+
+    # Fresh copies of the input for every step, staged in HBM before timing.
+    src_k, src_p = to_dev(wl.keys), to_dev(wl.payload)
+    nstep = args.warmup + args.steps
+    copies = [(src_k.clone(), src_p.clone()) for _ in range(nstep)]
+    M = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        binding.sort(copies[i][0], copies[i][1], min_run=args.min_run, merge_cost=M)
+    torch.cuda.synchronize()
+
+    binding.profile_enable(True)
+    binding.profile_read(reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.warmup, nstep):
+        binding.sort(copies[i][0], copies[i][1], min_run=args.min_run, merge_cost=M)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = binding.profile_read(reset=True)
+    binding.profile_enable(False)
+
+    wall_s = t1 - t0
+    ev_s = ev0.elapsed_time(ev1) / 1e3
+    step_s = wall_s / args.steps
+    merge_cost = int(M.item())
+
+    # Verify the last step against properties that fix the stable sort.
+    k_out, p_out = copies[-1]
+    kh = k_out.view(torch.int64 if kb == 8 else torch.int32).cpu().numpy()
+    ph = p_out.view(torch.int32).cpu().numpy().view(np.uint32)
+    okeys = wl.keys.view(np.int64 if kb == 8 else np.int32)
+    sorted_ok = bool(np.all(wl.keys[ph][1:] >= wl.keys[ph][:-1]))
+    seen = np.zeros(n, dtype=bool)
+    seen[ph] = True
+    perm_ok = bool(seen.all())
+    keys_ok = bool(np.array_equal(kh, okeys[ph]))
+    eq = wl.keys[ph][1:] == wl.keys[ph][:-1]
+    stable_ok = bool(np.all(ph[1:][eq] > ph[:-1][eq]))
+    if not (sorted_ok and perm_ok and keys_ok and stable_ok):
+        print(json.dumps({"error": "output is not the stable sort", "sorted": sorted_ok, "perm": perm_ok,
+                          "keys": keys_ok, "stable": stable_ok}))
+        return 1
+
+    if args.calib_copy_mib:
+        a = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # Roofline of the dominant kernel: the merge-path pass.  Algorithmic bytes
+    # per merged output element = read both inputs + write the result.
+    mp = prof["merge"]
+    mp_launch_ms = mp["ms"] / max(mp["launches"], 1)
+    mp_bytes = 2 * rec_bytes * mp["elems"]
+    mp_bytes_per_launch = mp_bytes / max(mp["launches"], 1)
+    achieved_gbs = (mp_bytes_per_launch / (mp_launch_ms / 1e3)) / 1e9 if mp_launch_ms > 0 else 0.0
+    peak_gbs = HBM_PEAK_BPS / 1e9
+    traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": peak_gbs, "unit": "GB/s",
+                "frac": round(achieved_gbs / peak_gbs, 4), "traffic": traffic,
+                "kernel": "merge_pass_kernel", "launch_ms": round(mp_launch_ms, 4),
+                "algorithmic_bytes_per_launch": int(mp_bytes_per_launch)}
+    # Whole path: B_alg = (K+V)(2M + 2n) per sort, from the merge cost.
+    b_alg = rec_bytes * (2 * merge_cost + 2 * n)
+    path = {"algorithmic_bytes": int(b_alg), "achieved_GBps": round(b_alg / step_s / 1e9, 1),
+            "frac": round(b_alg / step_s / HBM_PEAK_BPS, 4)}
+    groups = {g: {"ms_per_step": round(prof[g]["ms"] / args.steps, 4),
+                  "launches_per_step": prof[g]["launches"] // max(args.steps, 1),
+                  "elems_per_step": prof[g]["elems"] // max(args.steps, 1)}
+              for g in binding.PROF_GROUPS}
+
+    out = {
+        "metric": METRIC,
+        "value": round(n * args.steps / wall_s, 1),
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64" if kb == 8 else "int32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "key": str(wl.keys.dtype), "payload": "uint32 index",
+                   "min_run": args.min_run, "merge_cost": merge_cost, "merge_cost_per_key": round(merge_cost / n, 4),
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "path_roofline": path,
+        "kernel_groups": groups,
+        "event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
+        "gen_s": round(t_gen, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -129,6 +129,41 @@ typedef struct {
 ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_segments, uint64_t n_total,
                      ps_key_type key_type, const ps_options *opt, ps_inspect_out *out, void *stream);
 
+/* Kernel groups timed by the profiling mode. */
+enum {
+    PS_PROF_PARTITION = 0, /* run detection and leaf partition */
+    PS_PROF_TREE = 1,      /* powers, depths, merge cost */
+    PS_PROF_LISTS = 2,     /* node ranges and work lists */
+    PS_PROF_BIG_LEAF = 3,  /* copy / reversal of leaves longer than a fused subtree */
+    PS_PROF_FUSED = 4,     /* leaf formation and merges of subtrees held in LDS */
+    PS_PROF_MERGE = 5,     /* merge-path passes, one launch per node power */
+    PS_PROF_SPLIT = 6,     /* co-ranks of the merge-path tiles, one launch per node power */
+    PS_PROF_GROUPS = 7
+};
+
+/* Accumulated profile.  ms[g] is the summed duration of group g measured
+ * with HIP events recorded on the caller's stream around its launches;
+ * launches[g] counts those launches; elems[g] counts the elements the group
+ * processed (for PS_PROF_MERGE: merge outputs, i.e. the part of the merge cost
+ * M done by the merge-path passes; for PS_PROF_FUSED: elements of fused
+ * subtrees; for PS_PROF_BIG_LEAF: elements copied or reversed; otherwise n). */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t calls;
+    uint32_t launches[PS_PROF_GROUPS];
+    double ms[PS_PROF_GROUPS];
+    uint64_t elems[PS_PROF_GROUPS];
+} ps_profile;
+
+/* Turn the profiling mode on (1) or off (0) for subsequent calls of this
+ * process, for tools such as benchmarks.  It adds event records between
+ * launches and a few device atomics; results are unchanged. */
+ps_status ps_profile_enable(int on);
+
+/* Wait for the profiled work, add it to the running totals and copy them to
+ * *out; reset != 0 clears the totals afterwards. */
+ps_status ps_profile_read(ps_profile *out, int reset);
+
 /* Free the scratch memory the library holds for `stream` (synchronises it). */
 ps_status ps_release(void *stream);
 

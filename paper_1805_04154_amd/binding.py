@@ -22,7 +22,8 @@ KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, t
 
 # Every symbol include/powersort_hip.h declares.
 EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_segmented_sort", "ps_merge_cost", "ps_segmented_merge_cost",
-           "ps_inspect", "ps_release", "ps_status_string", "ps_last_error")
+           "ps_inspect", "ps_profile_enable", "ps_profile_read", "ps_release", "ps_status_string", "ps_last_error")
+PROF_GROUPS = ("partition", "tree", "lists", "big_leaf", "fused", "merge", "split")
 
 
 class PsOptions(ctypes.Structure):
@@ -33,6 +34,11 @@ class PsOptions(ctypes.Structure):
 class PsInspectOut(ctypes.Structure):
     _fields_ = [("starts", ctypes.c_void_p), ("powers", ctypes.c_void_p), ("node_left", ctypes.c_void_p),
                 ("node_right", ctypes.c_void_p), ("leaf_depth", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+
+
+class PsProfile(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("calls", ctypes.c_uint32),
+                ("launches", ctypes.c_uint32 * 7), ("ms", ctypes.c_double * 7), ("elems", ctypes.c_uint64 * 7)]
 
 
 class PowersortError(RuntimeError):
@@ -67,6 +73,10 @@ def load_library(path: str = LIB_PATH):
     lib.ps_segmented_merge_cost.argtypes = [vp, vp, u64, u64, i32, opt, vp, vp, vp]
     lib.ps_inspect.restype = i32
     lib.ps_inspect.argtypes = [vp, vp, u64, u64, i32, opt, ctypes.POINTER(PsInspectOut), vp]
+    lib.ps_profile_enable.restype = i32
+    lib.ps_profile_enable.argtypes = [i32]
+    lib.ps_profile_read.restype = i32
+    lib.ps_profile_read.argtypes = [ctypes.POINTER(PsProfile), i32]
     lib.ps_release.restype = i32
     lib.ps_release.argtypes = [vp]
     lib.ps_status_string.restype = ctypes.c_char_p
@@ -199,6 +209,22 @@ def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: in
     rr = int(r.item())
     return {"r": rr, "starts": starts[: rr + 1], "powers": powers[: rr + 1], "node_left": left[:rr],
             "node_right": right[:rr], "leaf_depth": depth[:rr]}
+
+
+def profile_enable(on: bool = True):
+    """Time the library's kernel groups with HIP events on the caller's stream."""
+    lib = load_library()
+    _check(lib.ps_profile_enable(int(on)))
+
+
+def profile_read(reset: bool = False) -> dict:
+    """Accumulated per-group {launches, ms, elems} since the last reset."""
+    lib = load_library()
+    p = PsProfile()
+    p.struct_size = ctypes.sizeof(PsProfile)
+    _check(lib.ps_profile_read(ctypes.byref(p), int(reset)))
+    return {"calls": p.calls,
+            **{g: {"launches": p.launches[i], "ms": p.ms[i], "elems": p.elems[i]} for i, g in enumerate(PROF_GROUPS)}}
 
 
 def release(stream=None):

@@ -3,6 +3,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/powersort_hip.h"
 #include "common.hpp"
@@ -72,8 +73,9 @@ struct Layout {
     uint32_t ntab[4];
     int levels;
     size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt;
-    size_t unit_a, unit_b, unit_par, bigleaf, bigleaf_mode, bucket, bucket_tile, leaf_tile;
+    size_t unit_rec, unit_par, bigleaf, bigleaf_mode, bucket, node_rec, bucket_tile, leaf_tile, split;
     uint32_t rmax;
+    uint64_t split_cap = 0;
 };
 
 static size_t take(size_t& at, size_t bytes) {
@@ -122,16 +124,22 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
     L.Lf = take(at, r1 * 4);
     L.Rt = take(at, r1 * 4);
     if (moves) {
-        L.unit_a = take(at, r1 * 4);
-        L.unit_b = take(at, r1 * 4);
+        L.unit_rec = take(at, r1 * sizeof(UnitRec));
         L.unit_par = take(at, r1);
         L.bigleaf = take(at, r1 * 4);
         L.bigleaf_mode = take(at, r1);
         L.bucket = take(at, r1 * 4);
+        L.node_rec = take(at, r1 * sizeof(NodeRec));
         L.bucket_tile = take(at, r1 * 4);
         L.leaf_tile = take(at, r1 * 4);
+        // merge tiles over all passes: sum of big-node sizes / tile + nodes,
+        // with the sum bounded by M <= n (lg n + 2) (Thm. "powersort")
+        const uint64_t lg = 64 - __builtin_clzll(N | 1);
+        L.split_cap = (N * (lg + 2)) / kMergeTile + r1 + 64;
+        L.split = take(at, L.split_cap * sizeof(SplitRec));
     } else {
-        L.unit_a = L.unit_b = L.unit_par = L.bigleaf = L.bigleaf_mode = L.bucket = L.bucket_tile = L.leaf_tile = 0;
+        L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
+        L.split = 0;
     }
     L.total = take(at, 0) + 256;
     return L;
@@ -193,6 +201,61 @@ static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* o
     p.device = dev;
     *out = ptr;
     return PS_OK;
+}
+
+// --------------------------------------------------------------- profiling
+
+struct ProfPending {
+    int group;
+    int launches;
+    uint64_t host_elems;
+    hipEvent_t a, b;
+};
+struct ProfState {
+    bool on = false;
+    std::vector<ProfPending> pending;
+    std::vector<hipEvent_t> pool;
+    ps_profile totals{};
+    unsigned long long* dev = nullptr;  // device element counters per group
+};
+static std::mutex g_prof_mu;
+static ProfState g_prof;
+
+static hipEvent_t prof_event() {
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets a group of launches with events on `st` when profiling is on.
+struct ProfScope {
+    bool active = false;
+    int group = 0, launches = 0;
+    uint64_t elems = 0;
+    hipEvent_t a = nullptr;
+    hipStream_t st = nullptr;
+    ProfScope(int g, int nl, uint64_t host_elems, hipStream_t s) : group(g), launches(nl), elems(host_elems), st(s) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof.on) return;
+        a = prof_event();
+        if (a && hipEventRecord(a, st) == hipSuccess) active = true;
+    }
+    ~ProfScope() {
+        if (!active) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        hipEvent_t b = prof_event();
+        if (b && hipEventRecord(b, st) == hipSuccess) g_prof.pending.push_back({group, launches, elems, a, b});
+    }
+};
+
+static bool prof_on() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof.on;
 }
 
 // ------------------------------------------------------------------ driver
@@ -270,7 +333,10 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     pa.starts = (uint32_t*)at(L.starts);
     pa.r_dev = (uint32_t*)cnt;  // Counters.r is its first word
     pa.rmax = L.rmax;
-    e = launch_partition(c.kt, pa, st);
+    {
+        ProfScope ps_(PS_PROF_PARTITION, 2 + 2 * L.levels, c.N, st);
+        e = launch_partition(c.kt, pa, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "partition launch");
 
     TreeArgs ta{};
@@ -291,7 +357,10 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     ta.mc = mc;
     ta.Lf = (uint32_t*)at(L.Lf);
     ta.Rt = (uint32_t*)at(L.Rt);
-    e = launch_tree_cost(ta, st);
+    {
+        ProfScope ps_(PS_PROF_TREE, 4, c.N, st);
+        e = launch_tree_cost(ta, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "tree launch");
 
     if (c.mode == Mode::Inspect) {
@@ -299,16 +368,23 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         if (e != hipSuccess) return hip_fail(e, "node-range launch");
     }
     if (moves) {
-        ta.lists.unit_a = (uint32_t*)at(L.unit_a);
-        ta.lists.unit_b = (uint32_t*)at(L.unit_b);
+        ta.lists.unit_rec = (UnitRec*)at(L.unit_rec);
         ta.lists.unit_par = (uint8_t*)at(L.unit_par);
         ta.lists.bigleaf = (uint32_t*)at(L.bigleaf);
         ta.lists.bigleaf_mode = (uint8_t*)at(L.bigleaf_mode);
         ta.lists.bucket = (uint32_t*)at(L.bucket);
+        ta.lists.node_rec = (NodeRec*)at(L.node_rec);
         ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
         ta.lists.leaf_tile = (uint32_t*)at(L.leaf_tile);
-        e = launch_node_ranges(ta, st);
-        if (e == hipSuccess) e = launch_tree_lists(c.kt, ta, st);
+        if (prof_on()) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            ta.prof = g_prof.dev;
+        }
+        {
+            ProfScope ps_(PS_PROF_LISTS, 6, c.N, st);
+            e = launch_node_ranges(ta, st);
+            if (e == hipSuccess) e = launch_tree_lists(c.kt, ta, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "tree-list launch");
         MoveArgs ma{};
         ma.keys[0] = c.keys;
@@ -321,19 +397,41 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.Rt = ta.Rt;
         ma.node_depth = ta.node_depth;
         ma.cnt = cnt;
-        ma.unit_a = ta.lists.unit_a;
-        ma.unit_b = ta.lists.unit_b;
+        ma.unit_rec = ta.lists.unit_rec;
         ma.unit_par = ta.lists.unit_par;
         ma.bigleaf = ta.lists.bigleaf;
         ma.bigleaf_mode = ta.lists.bigleaf_mode;
         ma.bucket = ta.lists.bucket;
+        ma.node_rec = ta.lists.node_rec;
         ma.bucket_tile = ta.lists.bucket_tile;
         ma.leaf_tile = ta.lists.leaf_tile;
+        ma.split = (SplitRec*)at(L.split);
+        ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, 2048);
-        e = launch_moves(c.kt, hp, ma, pmax, 1024, grid_fuse, 2048, st);
+        {
+            ProfScope ps_(PS_PROF_BIG_LEAF, 1, 0, st);
+            e = launch_move_stage(c.kt, hp, ma, 0, 0, 1024, st);
+        }
+        if (e == hipSuccess) {
+            ProfScope ps_(PS_PROF_FUSED, 1, 0, st);
+            e = launch_move_stage(c.kt, hp, ma, 1, 0, grid_fuse, st);
+        }
+        for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
+            {
+                ProfScope sp_(PS_PROF_SPLIT, 1, 0, st);
+                e = launch_move_stage(c.kt, hp, ma, 3, p, 1024, st);  // tile co-ranks of pass p
+            }
+            if (e != hipSuccess) break;
+            ProfScope ps_(PS_PROF_MERGE, 1, 0, st);
+            e = launch_move_stage(c.kt, hp, ma, 2, p, 2048, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
+        if (prof_on()) {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof.totals.calls++;
+        }
     }
     if (c.d_costs) {
         hipLaunchKernelGGL(copy_u64_kernel, dim3(std::min<uint32_t>(1024, (nseg + kThreads - 1) / kThreads + 1)),
@@ -449,6 +547,58 @@ ps_status ps_inspect(const void* keys, const uint64_t* d_offsets, uint64_t num_s
     Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, nullptr, nullptr, out,
            Mode::Inspect};
     return dispatch(c, opt, stream);
+}
+
+ps_status ps_profile_enable(int on) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (on && !g_prof.dev) {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(unsigned long long) * PS_PROF_GROUPS);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        e = hipMemset(p, 0, sizeof(unsigned long long) * PS_PROF_GROUPS);
+        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+        g_prof.dev = (unsigned long long*)p;
+    }
+    g_prof.on = on != 0;
+    return PS_OK;
+}
+
+ps_status ps_profile_read(ps_profile* out, int reset) {
+    g_last_error.clear();
+    if (!out || out->struct_size != sizeof(ps_profile)) return fail(PS_ERR_INVALID_ARG, "bad ps_profile");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ps_profile& T = g_prof.totals;
+    for (const ProfPending& p : g_prof.pending) {
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        T.ms[p.group] += ms;
+        T.launches[p.group] += p.launches;
+        T.elems[p.group] += p.host_elems;
+        g_prof.pool.push_back(p.a);
+        g_prof.pool.push_back(p.b);
+    }
+    g_prof.pending.clear();
+    unsigned long long dev[PS_PROF_GROUPS] = {0};
+    if (g_prof.dev) {
+        hipError_t e = hipMemcpy(dev, g_prof.dev, sizeof dev, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    const uint32_t size = out->struct_size;
+    *out = T;
+    out->struct_size = size;
+    for (int g = 0; g < PS_PROF_GROUPS; ++g) out->elems[g] += dev[g];
+    if (reset) {
+        g_prof.totals = ps_profile{};
+        if (g_prof.dev) {
+            hipError_t e = hipMemset(g_prof.dev, 0, sizeof dev);
+            if (e != hipSuccess) return hip_fail(e, "hipMemset");
+        }
+    }
+    return PS_OK;
 }
 
 ps_status ps_release(void* stream) {

@@ -13,19 +13,31 @@ struct Counters {
     uint32_t pfill[kMaxPower + 1];
     uint32_t pbase[kMaxPower + 1];
     uint32_t ptiles[kMaxPower + 1];  // merge tiles per power; [0] = big-leaf tiles
+    uint32_t sbase[kMaxPower + 1];   // first split record of each power's pass
 };
 
 struct Mask2 {
     uint64_t a, b;
 };
 
+struct NodeRec {
+    uint32_t lo, mid, hi, depth;  // a merge of [lo, mid) and [mid, hi); the node's depth
+};
+struct SplitRec {
+    uint32_t node;    // bucket entry of the tile's node
+    uint32_t corank;  // A elements before the tile's first output
+};
+struct UnitRec {
+    uint32_t ua, ub, lo, hi;  // leaves [ua, ub) spanning elements [lo, hi)
+};
+
 struct TreeLists {
-    uint32_t* unit_a;
-    uint32_t* unit_b;
+    UnitRec* unit_rec;
     uint8_t* unit_par;
     uint32_t* bigleaf;
     uint8_t* bigleaf_mode;
     uint32_t* bucket;       // big nodes grouped by power
+    NodeRec* node_rec;      // merge record of each bucket entry
     uint32_t* bucket_tile;  // first merge tile of each bucket entry (within its pass)
     uint32_t* leaf_tile;    // first copy tile of each big leaf
 };
@@ -49,6 +61,7 @@ struct TreeArgs {
     uint32_t* Lf;
     uint32_t* Rt;
     TreeLists lists;
+    unsigned long long* prof;  // profiling element counters (nullable), indexed by PS_PROF_* group
 };
 
 struct PartitionArgs {
@@ -77,14 +90,16 @@ struct MoveArgs {
     const uint32_t* Rt;
     const uint8_t* node_depth;
     const Counters* cnt;
-    const uint32_t* unit_a;
-    const uint32_t* unit_b;
+    const UnitRec* unit_rec;
     const uint8_t* unit_par;
     const uint32_t* bigleaf;
     const uint8_t* bigleaf_mode;
     const uint32_t* bucket;
+    const NodeRec* node_rec;
     const uint32_t* bucket_tile;
     const uint32_t* leaf_tile;
+    SplitRec* split;
+    uint32_t split_cap;  // capacity of split (records)
 };
 
 enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace = 3 };
@@ -94,7 +109,7 @@ hipError_t launch_init(Counters* cnt, uint64_t* mc, uint32_t nseg, hipStream_t s
 hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st);
 hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st);
 hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st);
-hipError_t launch_moves(int kt, bool hp, const MoveArgs& a, uint32_t pmax, uint32_t grid_leaf, uint32_t grid_fuse,
-                        uint32_t grid_merge, hipStream_t st);
+hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
+                             hipStream_t st);
 
 }  // namespace ps

@@ -40,6 +40,7 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__
 template <int KT, bool HP>
 __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
     using raw = typename Key<KT>::raw;
+    constexpr int kB = 16;  // elements per thread in flight
     const uint32_t ntiles = a.cnt->ptiles[0];
     const uint32_t nleaf = a.cnt->nbigleaf;
     raw* k0 = (raw*)a.keys[0];
@@ -53,24 +54,57 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
         const uint32_t x0 = (t - a.leaf_tile[k]) * kLeafTile;
         if (mode == kLeafRevInPlace) {
             const uint32_t x1 = min(L / 2, x0 + kLeafTile);
-            for (uint32_t x = x0 + threadIdx.x; x < x1; x += kThreads) {
-                const uint32_t y = L - 1 - x;
-                const raw kx = k0[s + x], ky = k0[s + y];
-                k0[s + x] = ky;
-                k0[s + y] = kx;
-                if (HP) {
-                    const uint32_t px = a.pay[0][s + x], py = a.pay[0][s + y];
-                    a.pay[0][s + x] = py;
-                    a.pay[0][s + y] = px;
+            for (uint32_t xb = x0; xb < x1; xb += kB * kThreads) {
+                raw kx[kB], ky[kB];
+                uint32_t px[kB], py[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const uint32_t x = xb + j * kThreads + threadIdx.x;
+                    if (x < x1) {
+                        kx[j] = k0[s + x];
+                        ky[j] = k0[s + L - 1 - x];
+                        if (HP) {
+                            px[j] = a.pay[0][s + x];
+                            py[j] = a.pay[0][s + L - 1 - x];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const uint32_t x = xb + j * kThreads + threadIdx.x;
+                    if (x < x1) {
+                        k0[s + x] = ky[j];
+                        k0[s + L - 1 - x] = kx[j];
+                        if (HP) {
+                            a.pay[0][s + x] = py[j];
+                            a.pay[0][s + L - 1 - x] = px[j];
+                        }
+                    }
                 }
             }
         } else {
             const uint32_t x1 = min(L, x0 + kLeafTile);
             const bool rev = (mode == kLeafRevCopy);
-            for (uint32_t x = x0 + threadIdx.x; x < x1; x += kThreads) {
-                const uint32_t y = rev ? (L - 1 - x) : x;
-                k1[s + y] = k0[s + x];
-                if (HP) a.pay[1][s + y] = a.pay[0][s + x];
+            for (uint32_t xb = x0; xb < x1; xb += kB * kThreads) {
+                raw kv[kB];
+                uint32_t pv[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const uint32_t x = xb + j * kThreads + threadIdx.x;
+                    if (x < x1) {
+                        kv[j] = k0[s + x];
+                        if (HP) pv[j] = a.pay[0][s + x];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const uint32_t x = xb + j * kThreads + threadIdx.x;
+                    if (x < x1) {
+                        const uint32_t y = rev ? (L - 1 - x) : x;
+                        k1[s + y] = kv[j];
+                        if (HP) a.pay[1][s + y] = pv[j];
+                    }
+                }
             }
         }
     }
@@ -102,16 +136,34 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
     const uint32_t nunits = a.cnt->nunits;
     const int tid = threadIdx.x;
     for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
-        const uint32_t ua = a.unit_a[u], ub = a.unit_b[u];
-        const uint32_t lo = a.starts[ua], n = a.starts[ub] - lo;
+        const UnitRec ur = a.unit_rec[u];
+        const uint32_t ua = ur.ua, ub = ur.ub;
+        const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         const uint32_t nleaves = ub - ua, nnodes = nleaves - 1;
         if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > (uint32_t)kFuseMaxNodes + 1) continue;
         const raw* src = (const raw*)a.keys[0];
-        raw* dst = (raw*)a.keys[a.unit_par[u]];
+        const uint32_t par = a.unit_par[u];
+        raw* dst = (raw*)a.keys[par];
         if (tid == 0) sm.pmask = 0;
-        for (uint32_t x = tid; x < n; x += kThreads) {
-            sm.sk[x] = K::ord(src[lo + x]);
-            if (HP) sm.sp[x] = a.pay[0][lo + x];
+        {
+            raw kv[kFuseItems];
+            uint32_t pv[kFuseItems];
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kThreads;
+                if (x < n) {
+                    kv[i] = src[lo + x];
+                    if (HP) pv[i] = a.pay[0][lo + x];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kThreads;
+                if (x < n) {
+                    sm.sk[x] = K::ord(kv[i]);
+                    if (HP) sm.sp[x] = pv[i];
+                }
+            }
         }
         for (uint32_t k = tid; k <= nleaves; k += kThreads) sm.lst[k] = (uint16_t)(a.starts[ua + k] - lo);
         __syncthreads();
@@ -264,9 +316,21 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
             }
             __syncthreads();
         }
-        for (uint32_t x = tid; x < n; x += kThreads) {
-            dst[lo + x] = K::unord(sm.sk[x]);
-            if (HP) a.pay[a.unit_par[u]][lo + x] = sm.sp[x];
+#pragma unroll
+        for (int i = 0; i < kFuseItems; ++i) {
+            const uint32_t x = tid + i * kThreads;
+            if (x < n) {
+                kr[i] = sm.sk[x];
+                if (HP) pr[i] = sm.sp[x];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kFuseItems; ++i) {
+            const uint32_t x = tid + i * kThreads;
+            if (x < n) {
+                dst[lo + x] = K::unord(kr[i]);
+                if (HP) a.pay[par][lo + x] = pr[i];
+            }
         }
         __syncthreads();
     }
@@ -283,41 +347,62 @@ struct MergeShared {
     uint32_t rng[4];
 };
 
-// Co-rank of diagonal d in the stable merge of A[0..la) and B[0..lb): the
-// number of A elements among the first d outputs (A goes first on equal
-// keys).  Each 128-thread half of the block searches its own diagonal; per
-// round its threads probe 128 evenly spaced candidates, so the range shrinks
-// 129-fold.  Both halves run the same number of rounds (block barriers).
-template <class K>
-__device__ uint32_t corank_kary(const typename K::raw* __restrict__ A, const typename K::raw* __restrict__ B,
-                                uint32_t la, uint32_t lb, uint32_t d, uint32_t* cnt_sh) {
-    const int t = threadIdx.x & 127;
-    const int half = threadIdx.x >> 7;
-    const int wid_in_half = (threadIdx.x >> 6) & 1;
-    uint32_t lo = d > lb ? d - lb : 0, hi = min(d, la);
-    while (__syncthreads_or(hi > lo)) {
-        const uint32_t span = hi - lo;
-        // probe g at m_g = lo + (g+1) span / 129 < hi; "taken" = A[m_g] is
-        // among the first d outputs, true for a prefix of the probes
-        bool taken = false;
-        if (span > 0) {
-            const uint32_t m = lo + (uint32_t)(((uint64_t)(t + 1) * span) / 129u);
-            taken = K::ord(A[m]) <= K::ord(B[d - 1 - m]);
+// Split pass: the merge-path co-rank at the start of every tile of pass p.
+// Co-rank of diagonal d in the stable merge of A = [lo, mid) and
+// B = [mid, hi): the number of A elements among the first d outputs, A going
+// first on equal keys.  Sixteen lanes search one tile: per round they probe
+// 16 evenly spaced candidates, shrinking the range 17-fold.
+constexpr int kSplitLanes = 16;
+
+template <int KT>
+__global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p) {
+    using K = Key<KT>;
+    using raw = typename K::raw;
+    const uint32_t ntiles = a.cnt->ptiles[p];
+    const uint32_t nb = a.cnt->pcount[p];
+    const uint32_t bbase = a.cnt->pbase[p];
+    if (nb == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int g16 = lane >> 4, l16 = lane & 15;
+    constexpr int kPerBlock = kThreads / kSplitLanes;
+    for (uint32_t tb = blockIdx.x * kPerBlock; tb < ntiles; tb += gridDim.x * kPerBlock) {
+        const uint32_t t = tb + (threadIdx.x >> 4);
+        const bool valid = t < ntiles;
+        uint32_t k = 0, lo_i = 0, hi_i = 0, d = 0;
+        const raw* A = nullptr;
+        const raw* B = nullptr;
+        if (valid) {
+            k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
+            const NodeRec R = a.node_rec[bbase + k];
+            const raw* src = (const raw*)a.keys[(R.depth + 1) & 1];
+            A = src + R.lo;
+            B = src + R.mid;
+            const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
+            d = (t - a.bucket_tile[bbase + k]) * kMergeTile;
+            lo_i = d > lb ? d - lb : 0;
+            hi_i = min(d, la);
         }
-        const uint64_t bal = __ballot(taken);
-        if ((threadIdx.x & 63) == 0) cnt_sh[half * 2 + wid_in_half] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        const uint32_t c = cnt_sh[half * 2] + cnt_sh[half * 2 + 1];
-        __syncthreads();
-        if (span > 0) {
-            // the answer lies in (m_{c-1}, m_c]
-            const uint32_t nlo = (c == 0) ? lo : lo + (uint32_t)(((uint64_t)c * span) / 129u) + 1;
-            const uint32_t nhi = (c >= 128) ? hi : lo + (uint32_t)(((uint64_t)(c + 1) * span) / 129u);
-            lo = nlo;
-            hi = max(nlo, nhi);
+        // the wave iterates until all four of its tiles are resolved
+        while (__ballot(hi_i > lo_i)) {
+            const uint32_t span = hi_i - lo_i;
+            bool taken = false;
+            if (span > 0) {
+                const uint32_t m = lo_i + (uint32_t)(((uint64_t)(l16 + 1) * span) / (kSplitLanes + 1));
+                taken = K::ord(A[m]) <= K::ord(B[d - 1 - m]);
+            }
+            const uint64_t bal = __ballot(taken);
+            const uint32_t c = (uint32_t)__popcll((bal >> (g16 * 16)) & 0xFFFFull);
+            if (span > 0) {
+                const uint32_t nlo = (c == 0) ? lo_i : lo_i + (uint32_t)(((uint64_t)c * span) / (kSplitLanes + 1)) + 1;
+                const uint32_t nhi =
+                    (c >= (uint32_t)kSplitLanes) ? hi_i : lo_i + (uint32_t)(((uint64_t)(c + 1) * span) / (kSplitLanes + 1));
+                lo_i = nlo;
+                hi_i = max(nlo, nhi);
+            }
         }
+        if (valid && l16 == 0 && a.cnt->sbase[p] + t < a.split_cap)
+            a.split[a.cnt->sbase[p] + t] = SplitRec{bbase + k, lo_i};
     }
-    return lo;
 }
 
 template <int KT, bool HP>
@@ -326,39 +411,50 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
     using U = typename K::ukey;
     using raw = typename K::raw;
     __shared__ MergeShared<KT> sm;
-    const uint32_t ntiles = a.cnt->ptiles[p];
-    const uint32_t nb = a.cnt->pcount[p];
-    const uint32_t bbase = a.cnt->pbase[p];
+    const uint32_t sb = a.cnt->sbase[p];
+    // never read past the split records (the tile count is bounded by the
+    // merge cost, so this only guards against inconsistent lists)
+    const uint32_t ntiles = min(a.cnt->ptiles[p], a.split_cap > sb + 1 ? a.split_cap - sb - 1 : 0u);
     const int tid = threadIdx.x;
-    if (nb == 0) return;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
-        const uint32_t j = a.bucket[bbase + k];
-        const uint32_t tt = t - a.bucket_tile[bbase + k];
-        const uint32_t lo = a.starts[a.Lf[j]], mid = a.starts[j], hi = a.starts[a.Rt[j]];
-        const uint32_t d = a.node_depth[j];
+        const SplitRec s0 = a.split[a.cnt->sbase[p] + t];
+        const NodeRec R = a.node_rec[s0.node];
+        const uint32_t tt = t - a.bucket_tile[s0.node];
+        const uint32_t lo = R.lo, mid = R.mid, hi = R.hi;
+        const uint32_t d = R.depth;
         const raw* src = (const raw*)a.keys[(d + 1) & 1];
         raw* dst = (raw*)a.keys[d & 1];
         const uint32_t* psrc = a.pay[(d + 1) & 1];
         uint32_t* pdst = a.pay[d & 1];
-        const uint32_t la = mid - lo, lb = hi - mid, tot = hi - lo;
+        const uint32_t la = mid - lo, tot = hi - lo;
         const uint32_t k0 = tt * kMergeTile, k1 = min(tot, k0 + kMergeTile);
-        const int half = tid >> 7;
-        const uint32_t dd = half ? k1 : k0;
-        const uint32_t ci = corank_kary<K>(src + lo, src + mid, la, lb, dd, sm.cnt);
-        if ((tid & 127) == 0) sm.rng[half] = ci;
-        __syncthreads();
-        const uint32_t i0 = sm.rng[0], i1 = sm.rng[1];
+        const uint32_t i0 = s0.corank;
+        const uint32_t i1 = (k1 == tot) ? la : a.split[a.cnt->sbase[p] + t + 1].corank;
         const uint32_t j0 = k0 - i0, j1 = k1 - i1;
         const uint32_t na = i1 - i0, nbb = j1 - j0, nt = na + nbb;
-        for (uint32_t x = tid; x < nt; x += kThreads) {
-            const uint32_t g = (x < na) ? (lo + i0 + x) : (mid + j0 + (x - na));
-            sm.sk[x] = K::ord(src[g]);
-            if (HP) sm.sp[x] = psrc[g];
-        }
-        __syncthreads();
         U kr[kMergeItems];
         uint32_t pr[kMergeItems];
+        {
+            raw kv[kMergeItems];
+#pragma unroll
+            for (int i = 0; i < kMergeItems; ++i) {
+                const uint32_t x = tid + i * kThreads;
+                if (x < nt) {
+                    const uint32_t g = (x < na) ? (lo + i0 + x) : (mid + j0 + (x - na));
+                    kv[i] = src[g];
+                    if (HP) pr[i] = psrc[g];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kMergeItems; ++i) {
+                const uint32_t x = tid + i * kThreads;
+                if (x < nt) {
+                    sm.sk[x] = K::ord(kv[i]);
+                    if (HP) sm.sp[x] = pr[i];
+                }
+            }
+        }
+        __syncthreads();
         const uint32_t dx = tid * kMergeItems;
         if (dx < nt) {
             uint32_t l = dx > nbb ? dx - nbb : 0, h = min(dx, na);
@@ -388,9 +484,21 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
             }
         }
         __syncthreads();
-        for (uint32_t x = tid; x < nt; x += kThreads) {
-            dst[lo + k0 + x] = K::unord(sm.sk[x]);
-            if (HP) pdst[lo + k0 + x] = sm.sp[x];
+#pragma unroll
+        for (int i = 0; i < kMergeItems; ++i) {
+            const uint32_t x = tid + i * kThreads;
+            if (x < nt) {
+                kr[i] = sm.sk[x];
+                if (HP) pr[i] = sm.sp[x];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kMergeItems; ++i) {
+            const uint32_t x = tid + i * kThreads;
+            if (x < nt) {
+                dst[lo + k0 + x] = K::unord(kr[i]);
+                if (HP) pdst[lo + k0 + x] = pr[i];
+            }
         }
         __syncthreads();
     }
@@ -399,29 +507,31 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
 // ------------------------------------------------------------- host launch
 
 template <int KT, bool HP>
-static hipError_t launch_moves_t(const MoveArgs& a, uint32_t pmax, uint32_t grid_leaf, uint32_t grid_fuse,
-                                 uint32_t grid_merge, hipStream_t st) {
-    hipLaunchKernelGGL((big_leaf_kernel<KT, HP>), dim3(grid_leaf), dim3(kThreads), 0, st, a);
-    hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid_fuse), dim3(kThreads), 0, st, a);
-    for (uint32_t p = pmax; p >= 1; --p)
-        hipLaunchKernelGGL((merge_pass_kernel<KT, HP>), dim3(grid_merge), dim3(kThreads), 0, st, a, p);
-    return hipGetLastError();
+static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st) {
+    if (stage == 0) hipLaunchKernelGGL((big_leaf_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (stage == 1) hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (stage == 2) hipLaunchKernelGGL((merge_pass_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a, p);
+    else hipLaunchKernelGGL((split_kernel<KT>), dim3(grid), dim3(kThreads), 0, st, a, p);
 }
 
-hipError_t launch_moves(int kt, bool hp, const MoveArgs& a, uint32_t pmax, uint32_t grid_leaf, uint32_t grid_fuse,
-                        uint32_t grid_merge, hipStream_t st) {
-#define PS_MOVES(KTV)                                                                                     \
-    return hp ? launch_moves_t<KTV, true>(a, pmax, grid_leaf, grid_fuse, grid_merge, st)                  \
-              : launch_moves_t<KTV, false>(a, pmax, grid_leaf, grid_fuse, grid_merge, st)
+// stage 0: big leaves; 1: fused subtrees; 2: the merge pass of power p;
+// 3: the split pass of power p.
+hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
+                             hipStream_t st) {
+#define PS_STAGE(KTV)                                                   \
+    if (hp) launch_stage_t<KTV, true>(a, stage, p, grid, st);           \
+    else launch_stage_t<KTV, false>(a, stage, p, grid, st);             \
+    break
     switch (kt) {
-    case KT_I32: PS_MOVES(KT_I32);
-    case KT_U32: PS_MOVES(KT_U32);
-    case KT_I64: PS_MOVES(KT_I64);
-    case KT_U64: PS_MOVES(KT_U64);
-    case KT_F32: PS_MOVES(KT_F32);
+    case KT_I32: PS_STAGE(KT_I32);
+    case KT_U32: PS_STAGE(KT_U32);
+    case KT_I64: PS_STAGE(KT_I64);
+    case KT_U64: PS_STAGE(KT_U64);
+    case KT_F32: PS_STAGE(KT_F32);
+    default: return hipErrorInvalidValue;
     }
-#undef PS_MOVES
-    return hipErrorInvalidValue;
+#undef PS_STAGE
+    return hipGetLastError();
 }
 
 }  // namespace ps

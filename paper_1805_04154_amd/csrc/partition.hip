@@ -67,9 +67,19 @@ __device__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, 
     const uint32_t WE = (uint32_t)min<uint64_t>((uint64_t)N, (uint64_t)T1 + w + 1);
     const uint32_t NPW = WE - T0 + 1;  // number of positions in the window = pairs
 
-    for (uint32_t k = tid; k < NPW; k += kThreads) {
-        if (k == 0 && T0 == 0) continue;
-        sm.u.keys[k] = K::ord(keys[T0 - 1 + k]);
+    {
+        // All of this thread's window loads are issued before the first use.
+        typename K::raw kv[kPairItems];
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i) {
+            const uint32_t k = tid + i * kThreads;
+            if (k < NPW && !(k == 0 && T0 == 0)) kv[i] = keys[T0 - 1 + k];
+        }
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i) {
+            const uint32_t k = tid + i * kThreads;
+            if (k < NPW && !(k == 0 && T0 == 0)) sm.u.keys[k] = K::ord(kv[i]);
+        }
     }
     if (tid == 0) {
         // First offset index whose value exceeds T0-1 (segment starts in the window).

@@ -320,7 +320,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                                                              const uint32_t* __restrict__ Rt,
                                                              const uint8_t* __restrict__ leaf_depth,
                                                              const uint8_t* __restrict__ node_depth,
-                                                             Counters* __restrict__ cnt, TreeLists L) {
+                                                             Counters* __restrict__ cnt, TreeLists L,
+                                                             unsigned long long* __restrict__ prof) {
     using K = Key<KT>;
     const uint32_t r = cnt->r;
     auto size_of = [&](uint32_t j) -> uint32_t { return starts[Rt[j]] - starts[Lf[j]]; };
@@ -336,6 +337,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             const uint32_t sz = starts[nrt] - starts[nlf];
             if (sz > (uint32_t)kFuse) {
                 big_node = true;
+                if (prof) atomicAdd(&prof[5], (unsigned long long)sz);
             } else {
                 const uint32_t pl = P[nlf], pr = P[nrt];
                 const uint32_t par = pl > pr ? nlf : (pr > pl ? nrt : kNone);
@@ -345,8 +347,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         if (big_node) atomicAdd(&cnt->pcount[P[i]], 1u);
         uint32_t slot = wave_append(unit_node, &cnt->nunits);
         if (unit_node) {
-            L.unit_a[slot] = nlf;
-            L.unit_b[slot] = nrt;
+            if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[nrt] - starts[nlf]));
+            L.unit_rec[slot] = UnitRec{nlf, nrt, starts[nlf], starts[nrt]};
             L.unit_par[slot] = node_depth[i] & 1;
         }
         // ---- leaf i
@@ -367,12 +369,13 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         }
         slot = wave_append(unit_leaf, &cnt->nunits);
         if (unit_leaf) {
-            L.unit_a[slot] = i;
-            L.unit_b[slot] = i + 1;
+            if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[i + 1] - starts[i]));
+            L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
             L.unit_par[slot] = leaf_depth[i] & 1;
         }
         slot = wave_append(big_leaf, &cnt->nbigleaf);
         if (big_leaf) {
+            if (prof && mode != kLeafNoop) atomicAdd(&prof[3], (unsigned long long)(starts[i + 1] - starts[i]));
             L.bigleaf[slot] = i;
             L.bigleaf_mode[slot] = mode;
         }
@@ -409,6 +412,7 @@ __global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint32_t
 __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __restrict__ starts,
                                                               const uint32_t* __restrict__ Lf,
                                                               const uint32_t* __restrict__ Rt,
+                                                              const uint8_t* __restrict__ node_depth,
                                                               Counters* __restrict__ cnt, TreeLists L) {
     __shared__ uint32_t sh[kWaves];
     const uint32_t p = blockIdx.x;
@@ -427,7 +431,9 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                 else if (mode != kLeafNoop) tiles = (len + kLeafTile - 1) / kLeafTile;
             } else {
                 const uint32_t j = L.bucket[off + k];
-                tiles = (starts[Rt[j]] - starts[Lf[j]] + kMergeTile - 1) / kMergeTile;
+                const uint32_t lo = starts[Lf[j]], hi = starts[Rt[j]];
+                L.node_rec[off + k] = NodeRec{lo, starts[j], hi, node_depth[j]};
+                tiles = (hi - lo + kMergeTile - 1) / kMergeTile;
             }
         }
         uint32_t total;
@@ -439,6 +445,18 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
         carry += total;
     }
     if (threadIdx.x == 0) cnt->ptiles[p] = carry;
+}
+
+// First split record of every pass.
+__global__ void pass_base_kernel(Counters* cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int p = 1; p <= kMaxPower; ++p) {
+            cnt->sbase[p] = acc;
+            acc += cnt->ptiles[p];
+        }
+        cnt->sbase[0] = acc;
+    }
 }
 
 // ------------------------------------------------------------- host launch
@@ -471,7 +489,7 @@ template <int KT>
 static void launch_classify_t(const TreeArgs& a, uint32_t g, hipStream_t st) {
     using raw = typename Key<KT>::raw;
     hipLaunchKernelGGL(classify_kernel<KT>, dim3(g), dim3(kThreads), 0, st, (const raw*)a.keys, a.starts, a.P, a.Lf,
-                       a.Rt, a.leaf_depth, a.node_depth, a.cnt, a.lists);
+                       a.Rt, a.leaf_depth, a.node_depth, a.cnt, a.lists, a.prof);
 }
 
 // Node ranges and the work lists of the data-movement phase.
@@ -494,8 +512,9 @@ hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gl), dim3(kThreads), 0, st, a.starts, a.P, a.Lf, a.Rt, a.cnt,
                        a.lists);
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt, a.cnt,
-                       a.lists);
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt,
+                       a.node_depth, a.cnt, a.lists);
+    hipLaunchKernelGGL(pass_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
     return hipGetLastError();
 }
 
