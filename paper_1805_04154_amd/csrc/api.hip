@@ -421,7 +421,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
             {
                 ProfScope sp_(PS_PROF_SPLIT, 1, 0, st);
-                e = launch_move_stage(c.kt, hp, ma, 3, p, 1024, st);  // tile co-ranks of pass p
+                e = launch_move_stage(c.kt, hp, ma, 3, p, 512, st);  // tile co-ranks of pass p
             }
             if (e != hipSuccess) break;
             ProfScope ps_(PS_PROF_MERGE, 1, 0, st);

@@ -347,13 +347,11 @@ struct MergeShared {
     uint32_t rng[4];
 };
 
-// Split pass: the merge-path co-rank at the start of every tile of pass p.
-// Co-rank of diagonal d in the stable merge of A = [lo, mid) and
-// B = [mid, hi): the number of A elements among the first d outputs, A going
-// first on equal keys.  Sixteen lanes search one tile: per round they probe
-// 16 evenly spaced candidates, shrinking the range 17-fold.
-constexpr int kSplitLanes = 16;
-
+// Split pass: the merge-path co-rank at the start of every tile of pass p,
+// one thread per tile.  Co-rank of diagonal d in the stable merge of
+// A = [lo, mid) and B = [mid, hi): the number of A elements among the first d
+// outputs, A going first on equal keys, by binary search.  All tiles of the
+// pass search at once; their first levels share cache lines.
 template <int KT>
 __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p) {
     using K = Key<KT>;
@@ -361,47 +359,22 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
     const uint32_t ntiles = a.cnt->ptiles[p];
     const uint32_t nb = a.cnt->pcount[p];
     const uint32_t bbase = a.cnt->pbase[p];
+    const uint32_t sb = a.cnt->sbase[p];
     if (nb == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int g16 = lane >> 4, l16 = lane & 15;
-    constexpr int kPerBlock = kThreads / kSplitLanes;
-    for (uint32_t tb = blockIdx.x * kPerBlock; tb < ntiles; tb += gridDim.x * kPerBlock) {
-        const uint32_t t = tb + (threadIdx.x >> 4);
-        const bool valid = t < ntiles;
-        uint32_t k = 0, lo_i = 0, hi_i = 0, d = 0;
-        const raw* A = nullptr;
-        const raw* B = nullptr;
-        if (valid) {
-            k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
-            const NodeRec R = a.node_rec[bbase + k];
-            const raw* src = (const raw*)a.keys[(R.depth + 1) & 1];
-            A = src + R.lo;
-            B = src + R.mid;
-            const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
-            d = (t - a.bucket_tile[bbase + k]) * kMergeTile;
-            lo_i = d > lb ? d - lb : 0;
-            hi_i = min(d, la);
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
+        const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
+        const NodeRec R = a.node_rec[bbase + k];
+        const raw* src = (const raw*)a.keys[(R.depth + 1) & 1];
+        const raw* A = src + R.lo;
+        const raw* B = src + R.mid;
+        const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
+        const uint32_t d = (t - a.bucket_tile[bbase + k]) * kMergeTile;
+        uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
+        while (l < h) {
+            const uint32_t m = (l + h) >> 1;
+            if (K::ord(A[m]) <= K::ord(B[d - 1 - m])) l = m + 1; else h = m;
         }
-        // the wave iterates until all four of its tiles are resolved
-        while (__ballot(hi_i > lo_i)) {
-            const uint32_t span = hi_i - lo_i;
-            bool taken = false;
-            if (span > 0) {
-                const uint32_t m = lo_i + (uint32_t)(((uint64_t)(l16 + 1) * span) / (kSplitLanes + 1));
-                taken = K::ord(A[m]) <= K::ord(B[d - 1 - m]);
-            }
-            const uint64_t bal = __ballot(taken);
-            const uint32_t c = (uint32_t)__popcll((bal >> (g16 * 16)) & 0xFFFFull);
-            if (span > 0) {
-                const uint32_t nlo = (c == 0) ? lo_i : lo_i + (uint32_t)(((uint64_t)c * span) / (kSplitLanes + 1)) + 1;
-                const uint32_t nhi =
-                    (c >= (uint32_t)kSplitLanes) ? hi_i : lo_i + (uint32_t)(((uint64_t)(c + 1) * span) / (kSplitLanes + 1));
-                lo_i = nlo;
-                hi_i = max(nlo, nhi);
-            }
-        }
-        if (valid && l16 == 0 && a.cnt->sbase[p] + t < a.split_cap)
-            a.split[a.cnt->sbase[p] + t] = SplitRec{bbase + k, lo_i};
+        if (sb + t < a.split_cap) a.split[sb + t] = SplitRec{bbase + k, l};
     }
 }
 

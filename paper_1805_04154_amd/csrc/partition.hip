@@ -57,7 +57,7 @@ struct PartShared {
 // the end of the natural run crossing T0 (kInf if none, kFar if beyond the
 // window).
 template <int KT>
-__device__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
+__device__ __forceinline__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
                                 const uint64_t* __restrict__ offsets, uint32_t nseg, uint32_t w,
                                 uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
     using K = Key<KT>;
@@ -81,7 +81,7 @@ __device__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, 
             if (k < NPW && !(k == 0 && T0 == 0)) sm.u.keys[k] = K::ord(kv[i]);
         }
     }
-    if (tid == 0) {
+    if (tid == 0 && nseg > 1) {
         // First offset index whose value exceeds T0-1 (segment starts in the window).
         uint32_t lo = 0, hi = nseg + 1;
         const uint64_t v = (uint64_t)T0;  // offsets > T0-1  <=>  offsets >= T0
@@ -101,7 +101,8 @@ __device__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, 
     }
     __syncthreads();
     // A segment start o in (T0-1, WE] breaks pair o-1: runs never cross it.
-    for (uint32_t g = sm.gfirst + tid; g <= nseg; g += kThreads) {
+    // (With one segment the only starts are 0 and N, handled above.)
+    for (uint32_t g = sm.gfirst + tid; nseg > 1 && g <= nseg; g += kThreads) {
         const uint64_t o = offsets[g];
         if (o > (uint64_t)WE) break;
         if (o >= 1 && o >= (uint64_t)T0) sm.pt[(uint32_t)(o - T0)] = kBreak;
@@ -313,13 +314,15 @@ template <int KT>
 __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
     uint32_t nseg, uint32_t w, const uint8_t* __restrict__ entry, const uint32_t* __restrict__ offs,
-    uint32_t* __restrict__ starts, uint32_t rcap) {
+    const uint32_t* __restrict__ tcnt, uint32_t* __restrict__ starts, uint32_t rcap) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
-    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
     const uint32_t e = entry[blockIdx.x];
+    // No leaf starts in this tile (e.g. it lies inside one long run).
+    if (tcnt[(size_t)blockIdx.x * (w + 1) + e] == 0) return;
+    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
     uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
     if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
     for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.em.mk[i] = (i == pos - T0);
@@ -381,7 +384,7 @@ hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
                            a.entry[l], a.offs[l], l == 0 ? a.r_dev : nullptr, a.starts, a.N, a.rmax);
     }
     hipLaunchKernelGGL(part_emit_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N, a.offsets,
-                       a.nseg, a.w, a.entry[0], a.offs[0], a.starts, a.rmax);
+                       a.nseg, a.w, a.entry[0], a.offs[0], a.cnt[0], a.starts, a.rmax);
     return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ Mask2 mshfl_down(Mask2 v, int d) {
 }
 
 // Exclusive forward (left-to-right) scan of thread aggregates over the block.
-__device__ Mask2 block_excl_fwd(Mask2 v, Mask2* sh) {
+__device__ __forceinline__ Mask2 block_excl_fwd(Mask2 v, Mask2* sh) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Mask2 incl = v;
 #pragma unroll
@@ -66,7 +66,7 @@ __device__ Mask2 block_excl_fwd(Mask2 v, Mask2* sh) {
 
 // Exclusive backward (right-to-left) scan: composition of all threads > tid,
 // rightmost first.
-__device__ Mask2 block_excl_bwd(Mask2 v, Mask2* sh) {
+__device__ __forceinline__ Mask2 block_excl_bwd(Mask2 v, Mask2* sh) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Mask2 incl = v;
 #pragma unroll
