@@ -5,7 +5,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/powersort_hip.h"
+#include "powersort_hip.h"
 #include "common.hpp"
 #include "block.hpp"
 #include "internal.hpp"

@@ -70,8 +70,8 @@ constexpr int kFuse = kThreads * kFuseItems;      // 4096
 constexpr int kFuseMaxNodes = kFuse / 2;          // internal nodes per subtree (w = 1 worst case)
 
 // Global merge passes: merge-path tiles of kMergeTile outputs.
-constexpr int kMergeItems = 16;
-constexpr int kMergeTile = kThreads * kMergeItems;  // 4096
+constexpr int kMergeItems = 8;
+constexpr int kMergeTile = kThreads * kMergeItems;  // 2048
 
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;
