@@ -72,8 +72,8 @@ struct Layout {
     size_t code[4], cnt[4], entry[4], offs[4];
     uint32_t ntab[4];
     int levels;
-    size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt;
-    size_t unit_rec, unit_par, bigleaf, bigleaf_mode, bucket, node_rec, bucket_tile, leaf_tile, split;
+    size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt, nsize;
+    size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split;
     uint32_t rmax;
     uint64_t split_cap = 0;
 };
@@ -123,11 +123,13 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
     L.mc = take(at, (nseg + 1) * 8);
     L.Lf = take(at, r1 * 4);
     L.Rt = take(at, r1 * 4);
+    L.nsize = take(at, r1 * 4);
     if (moves) {
         L.unit_rec = take(at, r1 * sizeof(UnitRec));
         L.unit_par = take(at, r1);
         L.bigleaf = take(at, r1 * 4);
         L.bigleaf_mode = take(at, r1);
+        L.biglist = take(at, r1 * 4);
         L.bucket = take(at, r1 * 4);
         L.node_rec = take(at, r1 * sizeof(NodeRec));
         L.bucket_tile = take(at, r1 * 4);
@@ -138,7 +140,7 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
         L.split_cap = (N * (lg + 2)) / kMergeTile + r1 + 64;
         L.split = take(at, L.split_cap * sizeof(SplitRec));
     } else {
-        L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
+        L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.biglist = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
         L.split = 0;
     }
     L.total = take(at, 0) + 256;
@@ -357,6 +359,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     ta.mc = mc;
     ta.Lf = (uint32_t*)at(L.Lf);
     ta.Rt = (uint32_t*)at(L.Rt);
+    ta.nsize = (uint32_t*)at(L.nsize);
     {
         ProfScope ps_(PS_PROF_TREE, 4, c.N, st);
         e = launch_tree_cost(ta, st);
@@ -372,6 +375,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ta.lists.unit_par = (uint8_t*)at(L.unit_par);
         ta.lists.bigleaf = (uint32_t*)at(L.bigleaf);
         ta.lists.bigleaf_mode = (uint8_t*)at(L.bigleaf_mode);
+        ta.lists.biglist = (uint32_t*)at(L.biglist);
         ta.lists.bucket = (uint32_t*)at(L.bucket);
         ta.lists.node_rec = (NodeRec*)at(L.node_rec);
         ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
@@ -407,12 +411,13 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.leaf_tile = ta.lists.leaf_tile;
         ma.split = (SplitRec*)at(L.split);
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
+        ma.fuse_max_leaves = fuse_max_leaves(c.w);
         const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, 2048);
         {
             ProfScope ps_(PS_PROF_BIG_LEAF, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 0, 0, 1024, st);
+            e = launch_move_stage(c.kt, hp, ma, 0, 0, 2048, st);
         }
         if (e == hipSuccess) {
             ProfScope ps_(PS_PROF_FUSED, 1, 0, st);

@@ -47,6 +47,30 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* sh, uin
 }
 
 
+// Exclusive prefix sum over a block of NW wave64s.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl_sum_w(uint32_t v, uint32_t* sh, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) sh[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) {
+        const uint32_t t = sh[w2];
+        before += (w2 < wid) ? t : 0u;
+        all += t;
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + incl - v;
+}
+
 // Exclusive prefix sum over the block for 64-bit values.
 __device__ __forceinline__ uint64_t block_excl_sum64(uint64_t v, uint64_t* sh, uint64_t* total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

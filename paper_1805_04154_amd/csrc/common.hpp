@@ -65,13 +65,18 @@ constexpr int kScanGroup = 128;                   // tables composed per group (
 
 // Fused subtrees: every maximal subtree of at most kFuse elements is formed
 // and merged entirely in LDS by one workgroup.
-constexpr int kFuseItems = 16;
-constexpr int kFuse = kThreads * kFuseItems;      // 4096
-constexpr int kFuseMaxNodes = kFuse / 2;          // internal nodes per subtree (w = 1 worst case)
+constexpr int kFuseThreads = 512;
+constexpr int kFuseWaves = kFuseThreads / 64;
+constexpr int kFuseItems = 8;
+constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
+// Leaves in a subtree of kFuse elements: at most kFuse / w + 1 (all but the
+// last leaf of a segment hold >= w elements; natural runs hold >= 2).
+__host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFuse / (w < 2 ? 2 : w) + 1; }
 
 // Global merge passes: merge-path tiles of kMergeTile outputs.
+constexpr int kMergeThreads = 512;
 constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kThreads * kMergeItems;  // 2048
+constexpr int kMergeTile = kMergeThreads * kMergeItems;  // 4096
 
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;

@@ -8,7 +8,7 @@ struct Counters {
     uint32_t r;            // number of leaves
     uint32_t nunits;       // fused subtrees
     uint32_t nbigleaf;     // leaves longer than kFuse
-    uint32_t error;
+    uint32_t nbig;         // nodes longer than kFuse
     uint32_t pcount[kMaxPower + 1];  // big nodes per power
     uint32_t pfill[kMaxPower + 1];
     uint32_t pbase[kMaxPower + 1];
@@ -36,6 +36,7 @@ struct TreeLists {
     uint8_t* unit_par;
     uint32_t* bigleaf;
     uint8_t* bigleaf_mode;
+    uint32_t* biglist;      // big nodes in discovery order
     uint32_t* bucket;       // big nodes grouped by power
     NodeRec* node_rec;      // merge record of each bucket entry
     uint32_t* bucket_tile;  // first merge tile of each bucket entry (within its pass)
@@ -60,6 +61,7 @@ struct TreeArgs {
     uint64_t* mc;
     uint32_t* Lf;
     uint32_t* Rt;
+    uint32_t* nsize;  // elements below node j
     TreeLists lists;
     unsigned long long* prof;  // profiling element counters (nullable), indexed by PS_PROF_* group
 };
@@ -99,7 +101,8 @@ struct MoveArgs {
     const uint32_t* bucket_tile;
     const uint32_t* leaf_tile;
     SplitRec* split;
-    uint32_t split_cap;  // capacity of split (records)
+    uint32_t split_cap;        // capacity of split (records)
+    uint32_t fuse_max_leaves;  // leaves a fused subtree can hold at this w
 };
 
 enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace = 3 };

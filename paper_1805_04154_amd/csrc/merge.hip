@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__
 template <int KT, bool HP>
 __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
     using raw = typename Key<KT>::raw;
-    constexpr int kB = 16;  // elements per thread in flight
+    constexpr int kB = 8;  // elements per thread in flight
     const uint32_t ntiles = a.cnt->ptiles[0];
     const uint32_t nleaf = a.cnt->nbigleaf;
     raw* k0 = (raw*)a.keys[0];
@@ -112,27 +112,50 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
 
 // ------------------------------------------------------- fused subtrees
 
-template <int KT>
-struct FuseShared {
-    using U = typename Key<KT>::ukey;
-    U sk[kFuse];
-    uint32_t sp[kFuse];
-    uint16_t lst[kFuse + 1];          // leaf starts (unit-relative), lst[nleaves] = n
-    uint16_t nlo[kFuseMaxNodes];      // node ranges [nlo, nhi), split at lst[m+1]
-    uint16_t nhi[kFuseMaxNodes];
-    uint8_t npw[kFuseMaxNodes];
-    uint16_t lvl[kFuseMaxNodes];      // nodes of the current power, in position order
-    uint32_t sh[kWaves];
-    unsigned long long pmask;
-    uint32_t nlvl;
+// Shared-memory layout (dynamic, sized from the largest number of leaves a
+// subtree of kFuse elements can hold, which depends on w).
+struct FuseLayout {
+    uint32_t sk, sp, lst, nlo, nhi, lvl, npw, bytes;
 };
+__host__ __device__ inline FuseLayout fuse_layout(uint32_t key_bytes, bool hp, uint32_t max_leaves) {
+    FuseLayout L;
+    uint32_t at = 128;  // wave totals and the power mask
+    L.sk = at;
+    at += kFuse * key_bytes;
+    L.sp = at;
+    at += hp ? kFuse * 4 : 0;
+    L.lst = at;
+    at += (max_leaves + 1) * 2;
+    L.nlo = at;
+    at += max_leaves * 2;
+    L.nhi = at;
+    at += max_leaves * 2;
+    L.lvl = at;
+    at += max_leaves * 2;
+    L.npw = at;
+    at += max_leaves;
+    L.bytes = (at + 15) & ~15u;
+    return L;
+}
 
 template <int KT, bool HP>
-__global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
+__global__ __launch_bounds__(kFuseThreads) void fused_kernel(MoveArgs a) {
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
-    __shared__ FuseShared<KT> sm;
+    extern __shared__ __align__(16) unsigned char fsm[];
+    const uint32_t ML = a.fuse_max_leaves;
+    const FuseLayout FL = fuse_layout(sizeof(U), HP, ML);
+    uint32_t* sh = reinterpret_cast<uint32_t*>(fsm);
+    unsigned long long* pmask = reinterpret_cast<unsigned long long*>(fsm + 64);
+    U* sk = reinterpret_cast<U*>(fsm + FL.sk);
+    uint32_t* sp = reinterpret_cast<uint32_t*>(fsm + FL.sp);
+    uint16_t* lst = reinterpret_cast<uint16_t*>(fsm + FL.lst);
+    uint16_t* snlo = reinterpret_cast<uint16_t*>(fsm + FL.nlo);
+    uint16_t* snhi = reinterpret_cast<uint16_t*>(fsm + FL.nhi);
+    uint16_t* lvl = reinterpret_cast<uint16_t*>(fsm + FL.lvl);
+    uint8_t* npw = fsm + FL.npw;
+
     const uint32_t nunits = a.cnt->nunits;
     const int tid = threadIdx.x;
     for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
@@ -140,47 +163,46 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
         const uint32_t ua = ur.ua, ub = ur.ub;
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         const uint32_t nleaves = ub - ua, nnodes = nleaves - 1;
-        if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > (uint32_t)kFuseMaxNodes + 1) continue;
+        if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > ML) continue;
         const raw* src = (const raw*)a.keys[0];
         const uint32_t par = a.unit_par[u];
         raw* dst = (raw*)a.keys[par];
-        if (tid == 0) sm.pmask = 0;
-        {
-            raw kv[kFuseItems];
-            uint32_t pv[kFuseItems];
-#pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = tid + i * kThreads;
-                if (x < n) {
-                    kv[i] = src[lo + x];
-                    if (HP) pv[i] = a.pay[0][lo + x];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = tid + i * kThreads;
-                if (x < n) {
-                    sm.sk[x] = K::ord(kv[i]);
-                    if (HP) sm.sp[x] = pv[i];
-                }
-            }
-        }
-        for (uint32_t k = tid; k <= nleaves; k += kThreads) sm.lst[k] = (uint16_t)(a.starts[ua + k] - lo);
-        __syncthreads();
-        unsigned long long pm = 0;
-        for (uint32_t m = tid; m < nnodes; m += kThreads) {
-            const uint32_t j = ua + 1 + m;
-            const uint32_t p = a.P[j];
-            sm.npw[m] = (uint8_t)p;
-            sm.nlo[m] = sm.lst[a.Lf[j] - ua];
-            sm.nhi[m] = sm.lst[a.Rt[j] - ua];
-            pm |= 1ull << p;
-        }
-        if (pm) atomicOr(&sm.pmask, pm);
-
-        // Leaf formation: each leaf is stably sorted in place.
+        if (tid == 0) *pmask = 0;
         U kr[kFuseItems];
         uint32_t pr[kFuseItems];
+        {
+            raw kv[kFuseItems];
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kFuseThreads;
+                if (x < n) {
+                    kv[i] = src[lo + x];
+                    if (HP) pr[i] = a.pay[0][lo + x];
+                }
+            }
+            for (uint32_t k = tid; k <= nleaves; k += kFuseThreads) lst[k] = (uint16_t)(a.starts[ua + k] - lo);
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kFuseThreads;
+                if (x < n) {
+                    sk[x] = K::ord(kv[i]);
+                    if (HP) sp[x] = pr[i];
+                }
+            }
+        }
+        __syncthreads();
+        unsigned long long pm = 0;
+        for (uint32_t m = tid; m < nnodes; m += kFuseThreads) {
+            const uint32_t j = ua + 1 + m;
+            const uint32_t p = a.P[j];
+            npw[m] = (uint8_t)p;
+            snlo[m] = lst[a.Lf[j] - ua];
+            snhi[m] = lst[a.Rt[j] - ua];
+            pm |= 1ull << p;
+        }
+        if (pm) atomicOr(pmask, pm);
+
+        // Leaf formation: each leaf is stably sorted in place.
         uint16_t np[kFuseItems];
         const uint32_t x0 = tid * kFuseItems;
 #pragma unroll
@@ -188,71 +210,65 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
             const uint32_t x = x0 + i;
             np[i] = 0;
             if (x < n) {
-                // leaf k: lst[k] <= x < lst[k+1]
+                // leaf l: lst[l] <= x < lst[l+1]
                 uint32_t l = 0, h = nleaves;
                 while (l + 1 < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (sm.lst[m] <= x) l = m; else h = m;
+                    const uint32_t mm = (l + h) >> 1;
+                    if (lst[mm] <= x) l = mm; else h = mm;
                 }
-                const uint32_t ls = sm.lst[l], le = sm.lst[l + 1];
-                const U key = sm.sk[x];
-                uint32_t dst_pos;
+                const uint32_t ls = lst[l], le = lst[l + 1];
+                const U key = sk[x];
+                uint32_t dpos;
                 if (le - ls <= (uint32_t)kMaxMinRun) {
                     uint32_t rank = 0;
                     for (uint32_t y = ls; y < le; ++y) {
-                        const U o = sm.sk[y];
+                        const U o = sk[y];
                         rank += (o < key) || (o == key && y < x);
                     }
-                    dst_pos = ls + rank;
+                    dpos = ls + rank;
                 } else {
                     // A leaf longer than any min-run extension is a natural run.
-                    const bool desc = sm.sk[ls + 1] < sm.sk[ls];
-                    dst_pos = desc ? (ls + le - 1 - x) : x;
+                    const bool desc = sk[ls + 1] < sk[ls];
+                    dpos = desc ? (ls + le - 1 - x) : x;
                 }
                 kr[i] = key;
-                pr[i] = HP ? sm.sp[x] : 0u;
-                np[i] = (uint16_t)dst_pos;
+                if (HP) pr[i] = sp[x];
+                np[i] = (uint16_t)dpos;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kFuseItems; ++i) {
             if (x0 + i < n) {
-                sm.sk[np[i]] = kr[i];
-                if (HP) sm.sp[np[i]] = pr[i];
+                sk[np[i]] = kr[i];
+                if (HP) sp[np[i]] = pr[i];
             }
         }
         __syncthreads();
 
-        // Internal merges, deepest power first.
-        unsigned long long rem = sm.pmask;
+        // Internal merges, deepest power first; nodes of one power are disjoint.
+        unsigned long long rem = *pmask;
         while (rem) {
             const uint32_t p = 63 - __clzll(rem);
             rem &= ~(1ull << p);
             // Nodes of power p in position order.
-            constexpr int kNodeItems = kFuseMaxNodes / kThreads;
-            uint32_t c = 0;
-#pragma unroll
-            for (int i = 0; i < kNodeItems; ++i) {
-                const uint32_t m = tid * kNodeItems + i;
-                c += (m < nnodes && sm.npw[m] == p);
-            }
-            uint32_t total;
-            uint32_t pos = block_excl_sum(c, sm.sh, &total);
-#pragma unroll
-            for (int i = 0; i < kNodeItems; ++i) {
-                const uint32_t m = tid * kNodeItems + i;
-                if (m < nnodes && sm.npw[m] == p) sm.lvl[pos++] = (uint16_t)m;
+            uint32_t nl = 0;
+            for (uint32_t c0 = 0; c0 < nnodes; c0 += kFuseThreads) {
+                const uint32_t m = c0 + tid;
+                const bool f = (m < nnodes) && npw[m] == p;
+                uint32_t tot;
+                const uint32_t pos = block_excl_sum_w<kFuseWaves>(f ? 1u : 0u, sh, &tot);
+                if (f) lvl[nl + pos] = (uint16_t)m;
+                nl += tot;
             }
             __syncthreads();
-            const uint32_t nl = total;
             // First node whose range ends after x0.
             uint32_t idx;
             {
                 uint32_t l = 0, h = nl;
                 while (l < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (sm.nhi[sm.lvl[m]] <= x0) l = m + 1; else h = m;
+                    const uint32_t mm = (l + h) >> 1;
+                    if (snhi[lvl[mm]] <= x0) l = mm + 1; else h = mm;
                 }
                 idx = l;
             }
@@ -260,15 +276,15 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
             uint32_t ia = 0, ib = 0, ea = 0, eb = 0;
             uint32_t next_lo = kNoneM;
             if (idx < nl) {
-                const uint32_t m = sm.lvl[idx];
-                const uint32_t nlo = sm.nlo[m], nmid = sm.lst[m + 1], nhi = sm.nhi[m];
+                const uint32_t m = lvl[idx];
+                const uint32_t nlo = snlo[m], nmid = lst[m + 1], nhi = snhi[m];
                 if (nlo <= x0 && x0 < n) {
                     // Merge-path co-rank of diagonal x0 - nlo (ties to the left run).
                     const uint32_t d = x0 - nlo, la = nmid - nlo, lb = nhi - nmid;
                     uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
                     while (l < h) {
                         const uint32_t mm = (l + h) >> 1;
-                        if (sm.sk[nlo + mm] <= sm.sk[nmid + d - 1 - mm]) l = mm + 1; else h = mm;
+                        if (sk[nlo + mm] <= sk[nmid + d - 1 - mm]) l = mm + 1; else h = mm;
                     }
                     ia = nlo + l;
                     ib = nmid + (d - l);
@@ -284,49 +300,49 @@ __global__ __launch_bounds__(kThreads) void fused_kernel(MoveArgs a) {
                 const uint32_t x = x0 + i;
                 if (x < n) {
                     if (!in_node && x == next_lo) {
-                        const uint32_t m = sm.lvl[idx];
+                        const uint32_t m = lvl[idx];
                         ia = next_lo;
-                        ib = ea = sm.lst[m + 1];
-                        eb = sm.nhi[m];
+                        ib = ea = lst[m + 1];
+                        eb = snhi[m];
                         in_node = true;
                     }
                     uint32_t srcpos;
                     if (in_node) {
-                        const bool take_a = (ib >= eb) || (ia < ea && sm.sk[ia] <= sm.sk[ib]);
+                        const bool take_a = (ib >= eb) || (ia < ea && sk[ia] <= sk[ib]);
                         srcpos = take_a ? ia++ : ib++;
                         if (x + 1 == eb) {
                             in_node = false;
                             ++idx;
-                            next_lo = (idx < nl) ? sm.nlo[sm.lvl[idx]] : kNoneM;
+                            next_lo = (idx < nl) ? snlo[lvl[idx]] : kNoneM;
                         }
                     } else {
                         srcpos = x;
                     }
-                    kr[i] = sm.sk[srcpos];
-                    if (HP) pr[i] = sm.sp[srcpos];
+                    kr[i] = sk[srcpos];
+                    if (HP) pr[i] = sp[srcpos];
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < kFuseItems; ++i) {
                 if (x0 + i < n) {
-                    sm.sk[x0 + i] = kr[i];
-                    if (HP) sm.sp[x0 + i] = pr[i];
+                    sk[x0 + i] = kr[i];
+                    if (HP) sp[x0 + i] = pr[i];
                 }
             }
             __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = tid + i * kThreads;
+            const uint32_t x = tid + i * kFuseThreads;
             if (x < n) {
-                kr[i] = sm.sk[x];
-                if (HP) pr[i] = sm.sp[x];
+                kr[i] = sk[x];
+                if (HP) pr[i] = sp[x];
             }
         }
 #pragma unroll
         for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = tid + i * kThreads;
+            const uint32_t x = tid + i * kFuseThreads;
             if (x < n) {
                 dst[lo + x] = K::unord(kr[i]);
                 if (HP) a.pay[par][lo + x] = pr[i];
@@ -379,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
 }
 
 template <int KT, bool HP>
-__global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32_t p) {
+__global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, uint32_t p) {
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
             raw kv[kMergeItems];
 #pragma unroll
             for (int i = 0; i < kMergeItems; ++i) {
-                const uint32_t x = tid + i * kThreads;
+                const uint32_t x = tid + i * kMergeThreads;
                 if (x < nt) {
                     const uint32_t g = (x < na) ? (lo + i0 + x) : (mid + j0 + (x - na));
                     kv[i] = src[g];
@@ -420,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
             }
 #pragma unroll
             for (int i = 0; i < kMergeItems; ++i) {
-                const uint32_t x = tid + i * kThreads;
+                const uint32_t x = tid + i * kMergeThreads;
                 if (x < nt) {
                     sm.sk[x] = K::ord(kv[i]);
                     if (HP) sm.sp[x] = pr[i];
@@ -459,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kMergeItems; ++i) {
-            const uint32_t x = tid + i * kThreads;
+            const uint32_t x = tid + i * kMergeThreads;
             if (x < nt) {
                 kr[i] = sm.sk[x];
                 if (HP) pr[i] = sm.sp[x];
@@ -467,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
         }
 #pragma unroll
         for (int i = 0; i < kMergeItems; ++i) {
-            const uint32_t x = tid + i * kThreads;
+            const uint32_t x = tid + i * kMergeThreads;
             if (x < nt) {
                 dst[lo + k0 + x] = K::unord(kr[i]);
                 if (HP) pdst[lo + k0 + x] = pr[i];
@@ -482,8 +498,17 @@ __global__ __launch_bounds__(kThreads) void merge_pass_kernel(MoveArgs a, uint32
 template <int KT, bool HP>
 static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st) {
     if (stage == 0) hipLaunchKernelGGL((big_leaf_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (stage == 1) hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (stage == 2) hipLaunchKernelGGL((merge_pass_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a, p);
+    else if (stage == 1) {
+        const uint32_t lds = fuse_layout(sizeof(typename Key<KT>::ukey), HP, a.fuse_max_leaves).bytes;
+        static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (gfx950 has 160 KiB)
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void*)fused_kernel<KT, HP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      160 * 1024);
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid), dim3(kFuseThreads), lds, st, a);
+    }
+    else if (stage == 2) hipLaunchKernelGGL((merge_pass_kernel<KT, HP>), dim3(grid), dim3(kMergeThreads), 0, st, a, p);
     else hipLaunchKernelGGL((split_kernel<KT>), dim3(grid), dim3(kThreads), 0, st, a, p);
 }
 

@@ -55,9 +55,11 @@ struct PartShared {
 // J(s): a tile-local index if J(s) < T1, else kExitBit | exit code.  The
 // result is left in sm.u.pj.nx[0] (aliased by sm.u.em.nx[0]); sm.x0 receives
 // the end of the natural run crossing T0 (kInf if none, kFar if beyond the
-// window).
+// window).  Returns true, without filling nx, when the whole tile lies
+// inside one natural run that extends past the window: then every J(s) is
+// the run's end, beyond the window (exit code w).
 template <int KT>
-__device__ __forceinline__ void tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
+__device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
                                 const uint64_t* __restrict__ offsets, uint32_t nseg, uint32_t w,
                                 uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
     using K = Key<KT>;
@@ -108,6 +110,22 @@ __device__ __forceinline__ void tile_successors(const typename Key<KT>::raw* __r
         if (o >= 1 && o >= (uint64_t)T0) sm.pt[(uint32_t)(o - T0)] = kBreak;
     }
     __syncthreads();
+
+    // Fast path: every pair from T0 to the end of the window has the same
+    // direction and the window ends inside the run, so every position of the
+    // tile jumps past the window (to the end of this run).
+    {
+        const uint8_t t1 = sm.pt[1];
+        int uniform = (t1 == kAsc || t1 == kDesc) && sm.pt[NPW - 1] == kUnknown;
+        for (uint32_t k = 1 + tid; uniform && k + 1 < NPW; k += kThreads) uniform = (sm.pt[k] == t1);
+        if (__syncthreads_and(uniform)) {
+            // the run through pair (T0-1, T0) either continues (same direction),
+            // or does not exist (a break), or ends at T0 inclusive
+            if (tid == 0) sm.x0 = (sm.pt[0] == t1) ? kFar : (sm.pt[0] == kBreak ? kInf : T0 + 1);
+            __syncthreads();
+            return true;
+        }
+    }
 
     // Per thread: pairs k = tid*kPairItems + i.
     uint8_t tp[kPairItems];
@@ -168,6 +186,7 @@ __device__ __forceinline__ void tile_successors(const typename Key<KT>::raw* __r
         sm.u.pj.nx[0][s - T0] = enc;
     }
     __syncthreads();
+    return false;
 }
 
 // Pass 1: per-tile exit tables.  For candidate c (c < w: position T0+c;
@@ -181,7 +200,17 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
-    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
+    const uint32_t W1 = w + 1;
+    if (tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm)) {
+        // Entering at T0 + c (< T1): one leaf start, then past the window.
+        // Entering at the crossing run's end: that end lies past the window.
+        for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
+            const bool via_run = (c == w) && sm.x0 == kFar;
+            tcode[(size_t)blockIdx.x * W1 + c] = (uint8_t)w;
+            tcnt[(size_t)blockIdx.x * W1 + c] = via_run ? 0u : 1u;
+        }
+        return;
+    }
 
     // Pointer jumping to the exits, counting visited positions.
     for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.pj.ct[0][i] = 1;
@@ -204,7 +233,6 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
         if (!__syncthreads_or(any)) break;
     }
 
-    const uint32_t W1 = w + 1;
     for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
         uint32_t pos;
         bool valid = true;
@@ -322,7 +350,15 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const uint32_t e = entry[blockIdx.x];
     // No leaf starts in this tile (e.g. it lies inside one long run).
     if (tcnt[(size_t)blockIdx.x * (w + 1) + e] == 0) return;
-    tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm);
+    if (tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm)) {
+        // Inside one long run: the only leaf start is the entry itself.
+        const uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
+        if (threadIdx.x == 0 && pos < T1) {
+            const uint32_t rank = offs[blockIdx.x];
+            if (rank < rcap) starts[rank] = pos;
+        }
+        return;
+    }
     uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
     if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
     for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.em.mk[i] = (i == pos - T0);

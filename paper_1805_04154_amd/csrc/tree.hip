@@ -269,7 +269,9 @@ __global__ __launch_bounds__(kThreads) void mask_apply_kernel(const uint8_t* __r
 __global__ __launch_bounds__(kThreads) void node_range_kernel(const uint64_t* __restrict__ Q,
                                                                const uint8_t* __restrict__ P,
                                                                const uint32_t* __restrict__ r_dev,
-                                                               uint32_t* __restrict__ Lf, uint32_t* __restrict__ Rt) {
+                                                               const uint32_t* __restrict__ starts,
+                                                               uint32_t* __restrict__ Lf, uint32_t* __restrict__ Rt,
+                                                               uint32_t* __restrict__ nsize) {
     const uint32_t r = *r_dev;
     for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < r; j += gridDim.x * kThreads) {
         const uint32_t p = P[j];
@@ -286,6 +288,7 @@ __global__ __launch_bounds__(kThreads) void node_range_kernel(const uint64_t* __
             if ((Q[m] >> sh) == key) up = m; else lo = m + 1;
         }
         Lf[j] = (uint32_t)lo;
+        const uint32_t left = (uint32_t)lo;
         // Right: last match in [j, r-1]; Q[j] matches.
         d = 1;
         while ((int64_t)j + d < (int64_t)r && (Q[j + d] >> sh) == key) d <<= 1;
@@ -296,7 +299,19 @@ __global__ __launch_bounds__(kThreads) void node_range_kernel(const uint64_t* __
             if ((Q[m] >> sh) == key) lo = m; else up = m - 1;
         }
         Rt[j] = (uint32_t)lo + 1;
+        nsize[j] = starts[lo + 1] - starts[left];
     }
+}
+
+// Appends over the whole block: one atomic per block and counter.
+__device__ __forceinline__ uint32_t block_append(bool pred, uint32_t* counter, uint32_t* sh, uint32_t* base_sh) {
+    uint32_t total;
+    const uint32_t pos = block_excl_sum(pred ? 1u : 0u, sh, &total);
+    if (threadIdx.x == 0) *base_sh = total ? atomicAdd(counter, total) : 0u;
+    __syncthreads();
+    const uint32_t base = *base_sh;
+    __syncthreads();
+    return pred ? base + pos : kNone;
 }
 
 __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
@@ -320,11 +335,14 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                                                              const uint32_t* __restrict__ Rt,
                                                              const uint8_t* __restrict__ leaf_depth,
                                                              const uint8_t* __restrict__ node_depth,
+                                                             const uint32_t* __restrict__ nsize,
                                                              Counters* __restrict__ cnt, TreeLists L,
                                                              unsigned long long* __restrict__ prof) {
     using K = Key<KT>;
+    __shared__ uint32_t sh[kWaves];
+    __shared__ uint32_t base_sh;
     const uint32_t r = cnt->r;
-    auto size_of = [&](uint32_t j) -> uint32_t { return starts[Rt[j]] - starts[Lf[j]]; };
+    auto size_of = [&](uint32_t j) -> uint32_t { return nsize[j]; };
     for (uint32_t i0 = blockIdx.x * kThreads; i0 < r; i0 += gridDim.x * kThreads) {
         const uint32_t i = i0 + threadIdx.x;
         const bool valid = i < r;
@@ -334,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         if (valid && i >= 1 && P[i] >= 1) {
             nlf = Lf[i];
             nrt = Rt[i];
-            const uint32_t sz = starts[nrt] - starts[nlf];
+            const uint32_t sz = nsize[i];
             if (sz > (uint32_t)kFuse) {
                 big_node = true;
                 if (prof) atomicAdd(&prof[5], (unsigned long long)sz);
@@ -344,8 +362,9 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                 unit_node = (par == kNone) || size_of(par) > (uint32_t)kFuse;
             }
         }
-        if (big_node) atomicAdd(&cnt->pcount[P[i]], 1u);
-        uint32_t slot = wave_append(unit_node, &cnt->nunits);
+        uint32_t slot = block_append(big_node, &cnt->nbig, sh, &base_sh);
+        if (big_node) L.biglist[slot] = i;
+        slot = block_append(unit_node, &cnt->nunits, sh, &base_sh);
         if (unit_node) {
             if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[nrt] - starts[nlf]));
             L.unit_rec[slot] = UnitRec{nlf, nrt, starts[nlf], starts[nrt]};
@@ -367,18 +386,53 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                 unit_leaf = (par == kNone) || size_of(par) > (uint32_t)kFuse;
             }
         }
-        slot = wave_append(unit_leaf, &cnt->nunits);
+        slot = block_append(unit_leaf, &cnt->nunits, sh, &base_sh);
         if (unit_leaf) {
             if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[i + 1] - starts[i]));
             L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
             L.unit_par[slot] = leaf_depth[i] & 1;
         }
-        slot = wave_append(big_leaf, &cnt->nbigleaf);
+        slot = block_append(big_leaf, &cnt->nbigleaf, sh, &base_sh);
         if (big_leaf) {
             if (prof && mode != kLeafNoop) atomicAdd(&prof[3], (unsigned long long)(starts[i + 1] - starts[i]));
             L.bigleaf[slot] = i;
             L.bigleaf_mode[slot] = mode;
         }
+    }
+}
+
+// Adds 1 per active lane to counter[key], one atomic per distinct key in
+// the wave; returns the lane's slot among those lanes (ordered by lane).
+__device__ __forceinline__ uint32_t wave_count_by_key(bool active, uint32_t key, uint32_t* counter) {
+    const int lane = threadIdx.x & 63;
+    uint32_t slot = kNone;
+    bool done = !active;
+    while (true) {
+        const uint64_t act = __ballot(!done);
+        if (!act) break;
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t kl = __shfl(key, leader);
+        const uint64_t same = __ballot(!done && key == kl);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counter[kl], (uint32_t)__popcll(same));
+        base = __shfl(base, leader);
+        if (!done && key == kl) {
+            slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+            done = true;
+        }
+    }
+    return slot;
+}
+
+// Big nodes per power.
+__global__ __launch_bounds__(kThreads) void bucket_count_kernel(const uint8_t* __restrict__ P,
+                                                                 Counters* __restrict__ cnt, TreeLists L) {
+    const uint32_t nbig = cnt->nbig;
+    for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
+        const uint32_t k = k0 + threadIdx.x;
+        const bool valid = k < nbig;
+        const uint32_t p = valid ? P[L.biglist[k]] : 0;
+        wave_count_by_key(valid, p, cnt->pcount);
     }
 }
 
@@ -393,18 +447,16 @@ __global__ void bucket_base_kernel(Counters* cnt) {
     }
 }
 
-__global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint32_t* __restrict__ starts,
-                                                                   const uint8_t* __restrict__ P,
-                                                                   const uint32_t* __restrict__ Lf,
-                                                                   const uint32_t* __restrict__ Rt,
+__global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint8_t* __restrict__ P,
                                                                    Counters* __restrict__ cnt, TreeLists L) {
-    const uint32_t r = cnt->r;
-    for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < r; j += gridDim.x * kThreads) {
-        const uint32_t p = P[j];
-        if (j == 0 || p == 0) continue;
-        if (starts[Rt[j]] - starts[Lf[j]] <= (uint32_t)kFuse) continue;
-        const uint32_t slot = atomicAdd(&cnt->pfill[p], 1u);
-        L.bucket[cnt->pbase[p] + slot] = j;
+    const uint32_t nbig = cnt->nbig;
+    for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
+        const uint32_t k = k0 + threadIdx.x;
+        const bool valid = k < nbig;
+        const uint32_t j = valid ? L.biglist[k] : 0;
+        const uint32_t p = valid ? P[j] : 0;
+        const uint32_t slot = wave_count_by_key(valid, p, cnt->pfill);
+        if (valid) L.bucket[cnt->pbase[p] + slot] = j;
     }
 }
 
@@ -489,13 +541,14 @@ template <int KT>
 static void launch_classify_t(const TreeArgs& a, uint32_t g, hipStream_t st) {
     using raw = typename Key<KT>::raw;
     hipLaunchKernelGGL(classify_kernel<KT>, dim3(g), dim3(kThreads), 0, st, (const raw*)a.keys, a.starts, a.P, a.Lf,
-                       a.Rt, a.leaf_depth, a.node_depth, a.cnt, a.lists, a.prof);
+                       a.Rt, a.leaf_depth, a.node_depth, a.nsize, a.cnt, a.lists, a.prof);
 }
 
 // Node ranges and the work lists of the data-movement phase.
 hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st) {
     const uint32_t gl = grid_for(a.rmax, 4096);
-    hipLaunchKernelGGL(node_range_kernel, dim3(gl), dim3(kThreads), 0, st, a.Q, a.P, &a.cnt->r, a.Lf, a.Rt);
+    hipLaunchKernelGGL(node_range_kernel, dim3(gl), dim3(kThreads), 0, st, a.Q, a.P, &a.cnt->r, a.starts, a.Lf, a.Rt,
+                       a.nsize);
     return hipGetLastError();
 }
 
@@ -509,9 +562,10 @@ hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
     case KT_F32: launch_classify_t<KT_F32>(a, gl, st); break;
     default: return hipErrorInvalidValue;
     }
+    const uint32_t gb = grid_for(a.rmax, 512);
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(gb), dim3(kThreads), 0, st, a.P, a.cnt, a.lists);
     hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
-    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gl), dim3(kThreads), 0, st, a.starts, a.P, a.Lf, a.Rt, a.cnt,
-                       a.lists);
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gb), dim3(kThreads), 0, st, a.P, a.cnt, a.lists);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt,
                        a.node_depth, a.cnt, a.lists);
     hipLaunchKernelGGL(pass_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);

@@ -208,3 +208,33 @@ def test_segmented_bad_offsets_reported(ps):
     ps.segmented_sort(k, None, off, status=status)
     torch.cuda.synchronize()
     assert int(status.item()) == -1
+
+
+def boundary_cases():
+    """Long runs whose boundaries sit at or next to 4096-position tile edges,
+    in both directions, plus runs that end exactly where a window ends."""
+    T = 4096
+    for edge in (T, 2 * T, 3 * T):
+        for delta in (-2, -1, 0, 1, 2):
+            b = edge + delta
+            n = 5 * T + 77
+            # strictly descending up to b (inclusive of b-1), ascending after
+            left = np.arange(b, 0, -1) * 3
+            right = np.arange(n - b) * 3 + 1
+            yield f"desc_then_asc_{b}", np.concatenate([left, right])
+            # ascending then strictly descending
+            yield f"asc_then_desc_{b}", np.concatenate([np.arange(b), 10 ** 6 - np.arange(n - b)])
+            # ascending, then a drop, then ascending (equal keys across the drop)
+            yield f"asc_drop_asc_{b}", np.concatenate([np.arange(b) // 5, np.arange(n - b) // 5])
+    for L in (T - 70, T - 65, T - 64, T + 60, T + 65):
+        v = np.concatenate([np.arange(L)[::-1], np.arange(2 * T) + 10 ** 5, np.arange(T)[::-1]])
+        yield f"window_edge_{L}", v
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 24, 64])
+def test_runs_at_tile_boundaries(ps, w):
+    for name, v in boundary_cases():
+        try:
+            check_sort(ps, v.astype(np.int32), w)
+        except AssertionError as e:
+            raise AssertionError(f"case {name} w {w}: {e}")
