@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E
 METRIC = "keys/s and % HBM roofline (2^28 int32+idx); batched/served vs plain; p50/p99"
-WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32")
+WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32", "batched")
+BATCHED_METRIC = "batched segmented sort keys/s vs plain per-array calls (4096 arrays, log-uniform sizes 2^10..2^22)"
 
 
 def make_workload(name: str, n: int):
@@ -84,6 +85,8 @@ def main() -> int:
     ap.add_argument("--min-run", type=int, default=24)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--segments", type=int, default=4096, help="arrays in the batched workload")
+    ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -92,6 +95,8 @@ def main() -> int:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the sort is single-device with no sharding or collectives", file=sys.stderr)
         return 2
+    if args.workload == "batched":
+        return run_batched(args)
 
     import torch
     from paper_1805_04154_amd import binding
@@ -206,6 +211,116 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_batched(args) -> int:
+    """4096 arrays of log-uniform sizes: plain per-array ps_sort calls vs one
+    ps_segmented_sort (eager and replayed as a captured hipGraph, with the
+    autotuned launch shape).  Every timed sort starts from the same unsorted
+    input, restored outside the timed region."""
+    import torch
+    from paper_1805_04154_amd import autotune, batched, binding, workloads as W
+
+    binding.load_library()
+    binding.set_tuning(None)
+    t_gen = time.perf_counter()
+    wl = W.batched_random_runs(nseg=args.segments)
+    t_gen = time.perf_counter() - t_gen
+    n, nseg = wl.n, args.segments
+    offs = wl.offsets.astype(np.int64)
+    src_k = batched.to_device(wl.keys)
+    src_p = batched.to_device(wl.payload)
+    b = batched.SegmentedBatch(wl.offsets, wl.keys.dtype, min_run=args.min_run)
+    s = torch.cuda.current_stream()
+
+    def restore():
+        b.load(src_k, src_p)
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            restore()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    def plain():
+        for g in range(nseg):
+            a, c = int(offs[g]), int(offs[g + 1])
+            binding.sort(b.keys[a:c], b.payload[a:c], min_run=args.min_run)
+
+    reps = max(1, args.steps)
+    plain()  # warm-up (grows the per-stream pool to the largest array)
+    torch.cuda.synchronize()
+    plain_ms = timed(plain, min(reps, 3))
+    b.sort()
+    torch.cuda.synchronize()
+    eager_ms = timed(b.sort, reps)
+    tuned = None
+    key = autotune.signature(n, nseg, torch.int32, args.min_run, "batched_")
+    if not args.no_tune:
+        tuned, results = autotune.tune(restore, b.sort, autotune.candidates(), reps=2)
+        autotune.save_cache(key, tuned, results[0][0])
+    restore()
+    b.capture()
+    graph_ms = timed(b.replay, reps)
+    # correctness of the last replay: per segment sorted, stable, a permutation
+    restore()
+    b.replay()
+    torch.cuda.synchronize()
+    kh = b.keys.cpu().numpy()
+    ph = b.payload.view(torch.int32).cpu().numpy().view(np.uint32)
+    seg_of = np.repeat(np.arange(nseg), np.diff(offs))
+    ok = bool(np.array_equal(seg_of[ph], seg_of)) and bool(np.array_equal(kh, wl.keys[ph]))
+    same = (seg_of[1:] == seg_of[:-1])
+    ok = ok and bool(np.all(kh[1:][same] >= kh[:-1][same]))
+    eq = same & (kh[1:] == kh[:-1])
+    ok = ok and bool(np.all(ph[1:][eq] > ph[:-1][eq]))
+    if not ok:
+        print(json.dumps({"error": "batched output is not the per-segment stable sort"}))
+        return 1
+    M = int(b.costs.cpu().numpy().view(np.uint64).sum())
+    b_alg = 8 * (2 * M + 2 * n)
+    binding.profile_enable(True)
+    binding.profile_read(reset=True)
+    restore()
+    torch.cuda.synchronize()
+    b.sort()
+    torch.cuda.synchronize()
+    prof = binding.profile_read(reset=True)
+    binding.profile_enable(False)
+    mp = prof["merge"]
+    mp_ms = mp["ms"] / max(mp["launches"], 1)
+    ach = (2 * 8 * mp["elems"] / max(mp["launches"], 1)) / (mp_ms / 1e3) / 1e9 if mp_ms > 0 else 0.0
+    best_ms = min(eager_ms, graph_ms)
+    out = {
+        "metric": BATCHED_METRIC,
+        "value": round(n / (graph_ms / 1e3), 1),
+        "unit": "keys/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(graph_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "segments": nseg, "key": "int32", "payload": "uint32 index",
+                   "min_run": args.min_run, "merge_cost": M, "tuning": binding.get_tuning()},
+        "plain": {"ms": round(plain_ms, 3), "keys_per_s": round(n / (plain_ms / 1e3), 1),
+                  "calls": nseg},
+        "batched_eager": {"ms": round(eager_ms, 3), "keys_per_s": round(n / (eager_ms / 1e3), 1)},
+        "batched_graph": {"ms": round(graph_ms, 3), "keys_per_s": round(n / (graph_ms / 1e3), 1)},
+        "speedup_vs_plain": round(plain_ms / best_ms, 2),
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_BPS / 1e9, "unit": "GB/s",
+                     "frac": round(ach / (HBM_PEAK_BPS / 1e9), 4), "traffic": None, "kernel": "merge_pass_kernel",
+                     "launch_ms": round(mp_ms, 4)},
+        "path_roofline": {"algorithmic_bytes": b_alg, "frac": round(b_alg / (best_ms / 1e3) / HBM_PEAK_BPS, 4)},
+        "gen_s": round(t_gen, 1),
+    }
     print(json.dumps(out), flush=True)
     return 0
 

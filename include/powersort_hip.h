@@ -129,6 +129,28 @@ typedef struct {
 ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_segments, uint64_t n_total,
                      ps_key_type key_type, const ps_options *opt, ps_inspect_out *out, void *stream);
 
+/* Launch shape of the data-movement kernels (process-wide).  Every value
+ * changes only speed, never results: grids are workgroup counts of
+ * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048
+ * or 4096.  Zero fields keep their current value.  Written by the project's
+ * autotuner for a workload; read back with ps_get_tuning. */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t grid_big_leaf;
+    uint32_t grid_fused;
+    uint32_t grid_merge;
+    uint32_t grid_split;
+    uint32_t merge_tile;
+} ps_tuning;
+
+/* Set (tuning != NULL) or reset to defaults (NULL) the launch shape.
+ * Returns PS_ERR_INVALID_ARG for a bad struct_size or merge_tile, and
+ * PS_ERR_UNSUPPORTED for a grid above 65536. */
+ps_status ps_set_tuning(const ps_tuning *tuning);
+
+/* Current launch shape. */
+ps_status ps_get_tuning(ps_tuning *out);
+
 /* Kernel groups timed by the profiling mode. */
 enum {
     PS_PROF_PARTITION = 0, /* run detection and leaf partition */

@@ -22,7 +22,9 @@ KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, t
 
 # Every symbol include/powersort_hip.h declares.
 EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_segmented_sort", "ps_merge_cost", "ps_segmented_merge_cost",
-           "ps_inspect", "ps_profile_enable", "ps_profile_read", "ps_release", "ps_status_string", "ps_last_error")
+           "ps_inspect", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable", "ps_profile_read", "ps_release",
+           "ps_status_string", "ps_last_error")
+TUNING_FIELDS = ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split", "merge_tile")
 PROF_GROUPS = ("partition", "tree", "lists", "big_leaf", "fused", "merge", "split")
 
 
@@ -34,6 +36,12 @@ class PsOptions(ctypes.Structure):
 class PsInspectOut(ctypes.Structure):
     _fields_ = [("starts", ctypes.c_void_p), ("powers", ctypes.c_void_p), ("node_left", ctypes.c_void_p),
                 ("node_right", ctypes.c_void_p), ("leaf_depth", ctypes.c_void_p), ("r", ctypes.c_void_p)]
+
+
+class PsTuning(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32)] + [(f, ctypes.c_uint32) for f in
+                                                     ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split",
+                                                      "merge_tile")]
 
 
 class PsProfile(ctypes.Structure):
@@ -73,6 +81,10 @@ def load_library(path: str = LIB_PATH):
     lib.ps_segmented_merge_cost.argtypes = [vp, vp, u64, u64, i32, opt, vp, vp, vp]
     lib.ps_inspect.restype = i32
     lib.ps_inspect.argtypes = [vp, vp, u64, u64, i32, opt, ctypes.POINTER(PsInspectOut), vp]
+    lib.ps_set_tuning.restype = i32
+    lib.ps_set_tuning.argtypes = [ctypes.POINTER(PsTuning)]
+    lib.ps_get_tuning.restype = i32
+    lib.ps_get_tuning.argtypes = [ctypes.POINTER(PsTuning)]
     lib.ps_profile_enable.restype = i32
     lib.ps_profile_enable.argtypes = [i32]
     lib.ps_profile_read.restype = i32
@@ -209,6 +221,27 @@ def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: in
     rr = int(r.item())
     return {"r": rr, "starts": starts[: rr + 1], "powers": powers[: rr + 1], "node_left": left[:rr],
             "node_right": right[:rr], "leaf_depth": depth[:rr]}
+
+
+def set_tuning(tuning: dict | None):
+    """Set the launch shape (dict with any of TUNING_FIELDS; None = defaults)."""
+    lib = load_library()
+    if tuning is None:
+        _check(lib.ps_set_tuning(None))
+        return
+    t = PsTuning()
+    t.struct_size = ctypes.sizeof(PsTuning)
+    for f in TUNING_FIELDS:
+        setattr(t, f, int(tuning.get(f, 0)))
+    _check(lib.ps_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning() -> dict:
+    lib = load_library()
+    t = PsTuning()
+    t.struct_size = ctypes.sizeof(PsTuning)
+    _check(lib.ps_get_tuning(ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
 
 
 def profile_enable(on: bool = True):

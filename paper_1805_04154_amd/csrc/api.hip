@@ -137,7 +137,7 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
         // merge tiles over all passes: sum of big-node sizes / tile + nodes,
         // with the sum bounded by M <= n (lg n + 2) (Thm. "powersort")
         const uint64_t lg = 64 - __builtin_clzll(N | 1);
-        L.split_cap = (N * (lg + 2)) / kMergeTile + r1 + 64;
+        L.split_cap = (N * (lg + 2)) / kMergeTileMin + r1 + 64;
         L.split = take(at, L.split_cap * sizeof(SplitRec));
     } else {
         L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.biglist = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
@@ -203,6 +203,16 @@ static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* o
     p.device = dev;
     *out = ptr;
     return PS_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+static std::mutex g_tune_mu;
+static Tuning g_tune;
+
+static Tuning current_tuning() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune;
 }
 
 // --------------------------------------------------------------- profiling
@@ -302,6 +312,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     const uint32_t N = (uint32_t)c.N;
     const uint32_t nseg = (uint32_t)c.nseg;
     const bool moves = (c.mode == Mode::Sort);
+    const Tuning tune = current_tuning();
     const bool hp = moves && c.payload != nullptr;
     const size_t kb = key_bytes(c.kt);
     const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves);
@@ -360,6 +371,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     ta.Lf = (uint32_t*)at(L.Lf);
     ta.Rt = (uint32_t*)at(L.Rt);
     ta.nsize = (uint32_t*)at(L.nsize);
+    ta.merge_tile = tune.merge_tile;
     {
         ProfScope ps_(PS_PROF_TREE, 4, c.N, st);
         e = launch_tree_cost(ta, st);
@@ -412,12 +424,13 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.split = (SplitRec*)at(L.split);
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         ma.fuse_max_leaves = fuse_max_leaves(c.w);
+        ma.merge_tile = tune.merge_tile;
         const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
-        const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, 2048);
+        const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
         {
             ProfScope ps_(PS_PROF_BIG_LEAF, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 0, 0, 2048, st);
+            e = launch_move_stage(c.kt, hp, ma, 0, 0, tune.grid_big_leaf, st);
         }
         if (e == hipSuccess) {
             ProfScope ps_(PS_PROF_FUSED, 1, 0, st);
@@ -426,11 +439,11 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
             {
                 ProfScope sp_(PS_PROF_SPLIT, 1, 0, st);
-                e = launch_move_stage(c.kt, hp, ma, 3, p, 512, st);  // tile co-ranks of pass p
+                e = launch_move_stage(c.kt, hp, ma, 3, p, tune.grid_split, st);  // tile co-ranks of pass p
             }
             if (e != hipSuccess) break;
             ProfScope ps_(PS_PROF_MERGE, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 2, p, 2048, st);
+            e = launch_move_stage(c.kt, hp, ma, 2, p, tune.grid_merge, st);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
         if (prof_on()) {
@@ -552,6 +565,41 @@ ps_status ps_inspect(const void* keys, const uint64_t* d_offsets, uint64_t num_s
     Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, nullptr, nullptr, out,
            Mode::Inspect};
     return dispatch(c, opt, stream);
+}
+
+ps_status ps_set_tuning(const ps_tuning* t) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tune = Tuning{};
+        return PS_OK;
+    }
+    if (t->struct_size != sizeof(ps_tuning)) return fail(PS_ERR_INVALID_ARG, "ps_tuning.struct_size mismatch");
+    if (t->merge_tile && t->merge_tile != 2048 && t->merge_tile != 4096)
+        return fail(PS_ERR_INVALID_ARG, "merge_tile must be 2048 or 4096");
+    const uint32_t grids[4] = {t->grid_big_leaf, t->grid_fused, t->grid_merge, t->grid_split};
+    for (uint32_t g : grids)
+        if (g > 65536) return fail(PS_ERR_UNSUPPORTED, "grid above 65536");
+    Tuning n = g_tune;
+    if (t->grid_big_leaf) n.grid_big_leaf = t->grid_big_leaf;
+    if (t->grid_fused) n.grid_fused = t->grid_fused;
+    if (t->grid_merge) n.grid_merge = t->grid_merge;
+    if (t->grid_split) n.grid_split = t->grid_split;
+    if (t->merge_tile) n.merge_tile = t->merge_tile;
+    g_tune = n;
+    return PS_OK;
+}
+
+ps_status ps_get_tuning(ps_tuning* out) {
+    g_last_error.clear();
+    if (!out || out->struct_size != sizeof(ps_tuning)) return fail(PS_ERR_INVALID_ARG, "bad ps_tuning");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    out->grid_big_leaf = g_tune.grid_big_leaf;
+    out->grid_fused = g_tune.grid_fused;
+    out->grid_merge = g_tune.grid_merge;
+    out->grid_split = g_tune.grid_split;
+    out->merge_tile = g_tune.merge_tile;
+    return PS_OK;
 }
 
 ps_status ps_profile_enable(int on) {

@@ -73,10 +73,11 @@ constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
 // last leaf of a segment hold >= w elements; natural runs hold >= 2).
 __host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFuse / (w < 2 ? 2 : w) + 1; }
 
-// Global merge passes: merge-path tiles of kMergeTile outputs.
-constexpr int kMergeThreads = 512;
+// Global merge passes: merge-path tiles of 8 outputs per thread, 4096
+// outputs (512 threads) by default, 2048 (256 threads) when tuned so.
 constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kMergeThreads * kMergeItems;  // 4096
+constexpr uint32_t kMergeTileDefault = 4096;
+constexpr uint32_t kMergeTileMin = 2048;
 
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;

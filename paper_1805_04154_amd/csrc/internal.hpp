@@ -63,6 +63,7 @@ struct TreeArgs {
     uint32_t* Rt;
     uint32_t* nsize;  // elements below node j
     TreeLists lists;
+    uint32_t merge_tile;  // outputs per merge-path tile
     unsigned long long* prof;  // profiling element counters (nullable), indexed by PS_PROF_* group
 };
 
@@ -103,6 +104,16 @@ struct MoveArgs {
     SplitRec* split;
     uint32_t split_cap;        // capacity of split (records)
     uint32_t fuse_max_leaves;  // leaves a fused subtree can hold at this w
+    uint32_t merge_tile;       // outputs per merge-path tile
+};
+
+// Launch shape chosen by the caller (ps_set_tuning) or the defaults.
+struct Tuning {
+    uint32_t grid_big_leaf = 2048;
+    uint32_t grid_fused = 2048;
+    uint32_t grid_merge = 2048;
+    uint32_t grid_split = 512;
+    uint32_t merge_tile = kMergeTileDefault;
 };
 
 enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace = 3 };

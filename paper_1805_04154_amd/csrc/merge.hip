@@ -354,13 +354,11 @@ __global__ __launch_bounds__(kFuseThreads) void fused_kernel(MoveArgs a) {
 
 // ------------------------------------------------------------ merge passes
 
-template <int KT>
+template <int KT, int TILE>
 struct MergeShared {
     using U = typename Key<KT>::ukey;
-    U sk[kMergeTile];
-    uint32_t sp[kMergeTile];
-    uint32_t cnt[4];
-    uint32_t rng[4];
+    U sk[TILE];
+    uint32_t sp[TILE];
 };
 
 // Split pass: the merge-path co-rank at the start of every tile of pass p,
@@ -384,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
         const raw* A = src + R.lo;
         const raw* B = src + R.mid;
         const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
-        const uint32_t d = (t - a.bucket_tile[bbase + k]) * kMergeTile;
+        const uint32_t d = (t - a.bucket_tile[bbase + k]) * a.merge_tile;
         uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
         while (l < h) {
             const uint32_t m = (l + h) >> 1;
@@ -394,12 +392,14 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
     }
 }
 
-template <int KT, bool HP>
-__global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, uint32_t p) {
+// NT threads x kMergeItems outputs per tile (the tile size a.merge_tile).
+template <int KT, bool HP, int NT>
+__global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) {
+    constexpr int TILE = NT * kMergeItems;
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
-    __shared__ MergeShared<KT> sm;
+    __shared__ MergeShared<KT, TILE> sm;
     const uint32_t sb = a.cnt->sbase[p];
     // never read past the split records (the tile count is bounded by the
     // merge cost, so this only guards against inconsistent lists)
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, u
         const uint32_t* psrc = a.pay[(d + 1) & 1];
         uint32_t* pdst = a.pay[d & 1];
         const uint32_t la = mid - lo, tot = hi - lo;
-        const uint32_t k0 = tt * kMergeTile, k1 = min(tot, k0 + kMergeTile);
+        const uint32_t k0 = tt * TILE, k1 = min(tot, k0 + TILE);
         const uint32_t i0 = s0.corank;
         const uint32_t i1 = (k1 == tot) ? la : a.split[a.cnt->sbase[p] + t + 1].corank;
         const uint32_t j0 = k0 - i0, j1 = k1 - i1;
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, u
             raw kv[kMergeItems];
 #pragma unroll
             for (int i = 0; i < kMergeItems; ++i) {
-                const uint32_t x = tid + i * kMergeThreads;
+                const uint32_t x = tid + i * NT;
                 if (x < nt) {
                     const uint32_t g = (x < na) ? (lo + i0 + x) : (mid + j0 + (x - na));
                     kv[i] = src[g];
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, u
             }
 #pragma unroll
             for (int i = 0; i < kMergeItems; ++i) {
-                const uint32_t x = tid + i * kMergeThreads;
+                const uint32_t x = tid + i * NT;
                 if (x < nt) {
                     sm.sk[x] = K::ord(kv[i]);
                     if (HP) sm.sp[x] = pr[i];
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, u
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kMergeItems; ++i) {
-            const uint32_t x = tid + i * kMergeThreads;
+            const uint32_t x = tid + i * NT;
             if (x < nt) {
                 kr[i] = sm.sk[x];
                 if (HP) pr[i] = sm.sp[x];
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kMergeThreads) void merge_pass_kernel(MoveArgs a, u
         }
 #pragma unroll
         for (int i = 0; i < kMergeItems; ++i) {
-            const uint32_t x = tid + i * kMergeThreads;
+            const uint32_t x = tid + i * NT;
             if (x < nt) {
                 dst[lo + k0 + x] = K::unord(kr[i]);
                 if (HP) pdst[lo + k0 + x] = pr[i];
@@ -508,7 +508,12 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         }
         hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid), dim3(kFuseThreads), lds, st, a);
     }
-    else if (stage == 2) hipLaunchKernelGGL((merge_pass_kernel<KT, HP>), dim3(grid), dim3(kMergeThreads), 0, st, a, p);
+    else if (stage == 2) {
+        if (a.merge_tile == 2048)
+            hipLaunchKernelGGL((merge_pass_kernel<KT, HP, 256>), dim3(grid), dim3(256), 0, st, a, p);
+        else
+            hipLaunchKernelGGL((merge_pass_kernel<KT, HP, 512>), dim3(grid), dim3(512), 0, st, a, p);
+    }
     else hipLaunchKernelGGL((split_kernel<KT>), dim3(grid), dim3(kThreads), 0, st, a, p);
 }
 

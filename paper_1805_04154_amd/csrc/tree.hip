@@ -465,7 +465,8 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                                                               const uint32_t* __restrict__ Lf,
                                                               const uint32_t* __restrict__ Rt,
                                                               const uint8_t* __restrict__ node_depth,
-                                                              Counters* __restrict__ cnt, TreeLists L) {
+                                                              Counters* __restrict__ cnt, TreeLists L,
+                                                              uint32_t merge_tile) {
     __shared__ uint32_t sh[kWaves];
     const uint32_t p = blockIdx.x;
     const uint32_t n = (p == 0) ? cnt->nbigleaf : cnt->pcount[p];
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                 const uint32_t j = L.bucket[off + k];
                 const uint32_t lo = starts[Lf[j]], hi = starts[Rt[j]];
                 L.node_rec[off + k] = NodeRec{lo, starts[j], hi, node_depth[j]};
-                tiles = (hi - lo + kMergeTile - 1) / kMergeTile;
+                tiles = (hi - lo + merge_tile - 1) / merge_tile;
             }
         }
         uint32_t total;
@@ -567,7 +568,7 @@ hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gb), dim3(kThreads), 0, st, a.P, a.cnt, a.lists);
     hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt,
-                       a.node_depth, a.cnt, a.lists);
+                       a.node_depth, a.cnt, a.lists, a.merge_tile);
     hipLaunchKernelGGL(pass_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
     return hipGetLastError();
 }

@@ -20,6 +20,7 @@ Payloads are the original indices (``arange(n, dtype=uint32)``).
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -192,20 +193,58 @@ def zipf_runs(n: int = 1 << 28, key_dtype=np.uint64, seed_index: int = 2) -> Wor
     return Workload(f"zipf_runs_n{n}_{tag}", keys.astype(key_dtype), payload_for(n))
 
 
+def _segment_keys(args):
+    """Worker: random-runs keys for one segment, written into shared memory."""
+    shm_name, dtype, a, b, seq = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        out = np.ndarray((b,), dtype=dtype, buffer=shm.buf)
+        m = b - a
+        rng = np.random.Generator(np.random.PCG64(seq))
+        out[a:b] = random_runs(rng, m, math.sqrt(m), 0.25).astype(dtype)
+    finally:
+        shm.close()
+    return 0
+
+
 def batched_random_runs(nseg: int = 4096, lo_exp: int = 10, hi_exp: int = 22, desc_frac: float = 0.25,
-                        seed_index: int = 3, key_dtype=np.int32) -> Workload:
+                        seed_index: int = 3, key_dtype=np.int32, workers: int | None = None) -> Workload:
     """``nseg`` arrays with sizes log-uniform in [2^lo_exp, 2^hi_exp], each a
-    random-runs input with mean run length sqrt(size), 25% of runs reversed."""
+    random-runs input with mean run length sqrt(size), 25% of runs reversed.
+
+    Segment g draws from its own generator (spawned from the workload seed),
+    so the result does not depend on the number of worker processes."""
     rng = config_rng(seed_index)
     sizes = np.floor(np.exp(rng.uniform(lo_exp * math.log(2), hi_exp * math.log(2), size=nseg))).astype(np.int64)
     offsets = np.zeros(nseg + 1, np.uint64)
     offsets[1:] = np.cumsum(sizes)
     total = int(offsets[-1])
-    keys = np.empty(total, key_dtype)
-    for g in range(nseg):
-        a, b = int(offsets[g]), int(offsets[g + 1])
-        m = b - a
-        keys[a:b] = random_runs(rng, m, math.sqrt(m), desc_frac).astype(key_dtype)
+    seqs = np.random.SeedSequence(BASE_SEED + 100 + seed_index).spawn(nseg)
+    dt = np.dtype(key_dtype)
+    if desc_frac != 0.25:
+        raise ValueError("the batched workload reverses 25% of its runs")
+    workers = workers or min(16, os.cpu_count() or 1)
+    if total < (1 << 22) or workers <= 1:
+        keys = np.empty(total, dt)
+        for g in range(nseg):
+            a, b = int(offsets[g]), int(offsets[g + 1])
+            keys[a:b] = random_runs(np.random.Generator(np.random.PCG64(seqs[g])), b - a,
+                                    math.sqrt(b - a), 0.25).astype(dt)
+    else:
+        import multiprocessing as mp
+        from multiprocessing import shared_memory
+        shm = shared_memory.SharedMemory(create=True, size=max(1, total * dt.itemsize))
+        try:
+            jobs = [(shm.name, dt, int(offsets[g]), int(offsets[g + 1]), seqs[g]) for g in range(nseg)]
+            jobs.sort(key=lambda j: j[2] - j[3])  # largest first
+            with mp.get_context("fork").Pool(workers) as pool:
+                for _ in pool.imap_unordered(_segment_keys, jobs, chunksize=4):
+                    pass
+            keys = np.ndarray((total,), dtype=dt, buffer=shm.buf).copy()
+        finally:
+            shm.close()
+            shm.unlink()
     return Workload(f"batched_{nseg}_logu{lo_exp}-{hi_exp}", keys, payload_for(total), offsets)
 
 

@@ -75,3 +75,19 @@ def test_workspace_bytes(lib):
     assert lib.ps_workspace_bytes(10, 0, 0, 1, None) == 0
     assert lib.ps_workspace_bytes(10, 1, 9, 1, None) == 0
     assert lib.ps_workspace_bytes(10, 1, 0, 1, _opts(binding, min_run=99)) == 0
+
+
+def test_tuning_roundtrip_on_host():
+    from paper_1805_04154_amd import binding
+    binding.set_tuning(None)
+    d = binding.get_tuning()
+    assert d["merge_tile"] == 4096
+    binding.set_tuning({"merge_tile": 2048, "grid_merge": 333})
+    d2 = binding.get_tuning()
+    assert d2["merge_tile"] == 2048 and d2["grid_merge"] == 333 and d2["grid_fused"] == d["grid_fused"]
+    with pytest.raises(binding.PowersortError):
+        binding.set_tuning({"merge_tile": 1000})
+    with pytest.raises(binding.PowersortError):
+        binding.set_tuning({"grid_split": 1 << 20})
+    binding.set_tuning(None)
+    assert binding.get_tuning() == d
