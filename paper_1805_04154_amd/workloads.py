@@ -267,26 +267,89 @@ class Request:
     payload: np.ndarray
 
 
-def request_trace(rate_hz: float = 2000.0, duration_s: float = 1.0, lo_exp: int = 12, hi_exp: int = 24,
-                  seed_index: int = 4, max_requests: int | None = None) -> list[Request]:
-    """Open-loop request trace: exponential inter-arrival times at ``rate_hz``,
+@dataclass
+class RequestMeta:
+    arrival_s: float
+    n: int
+    dtype: np.dtype
+    seq: object  # numpy SeedSequence of the request's contents
+
+
+def trace_meta(rate_hz: float = 2000.0, duration_s: float = 1.0, lo_exp: int = 12, hi_exp: int = 24,
+               seed_index: int = 4, max_requests: int | None = None) -> list[RequestMeta]:
+    """Open-loop arrivals: exponential inter-arrival times at ``rate_hz``,
     sizes log-uniform in [2^lo_exp, 2^hi_exp], key dtype uniform over
-    {int32, int64, float32}, random-runs contents, uint32 payload."""
+    {int32, int64, float32}; each request carries the seed of its contents."""
     rng = config_rng(seed_index)
     t = 0.0
-    out: list[Request] = []
+    out: list[RequestMeta] = []
+    kinds = (np.dtype(np.int32), np.dtype(np.int64), np.dtype(np.float32))
     while True:
         t += rng.exponential(1.0 / rate_hz)
         if t > duration_s or (max_requests is not None and len(out) >= max_requests):
             break
         m = int(math.floor(math.exp(rng.uniform(lo_exp * math.log(2), hi_exp * math.log(2)))))
-        vals = random_runs(rng, m, math.sqrt(m), 0.25)
-        kind = int(rng.integers(0, 3))
-        if kind == 0:
-            keys = (vals - m // 2).astype(np.int32)
-        elif kind == 1:
-            keys = (vals - m // 2).astype(np.int64) * np.int64(1 << 20)
-        else:
-            keys = f32_from_values(rng, vals, m)
-        out.append(Request(t, keys, payload_for(m)))
+        out.append(RequestMeta(t, m, kinds[int(rng.integers(0, 3))], None))
+    seqs = np.random.SeedSequence(BASE_SEED + 200 + seed_index).spawn(len(out))
+    for r, q in zip(out, seqs):
+        r.seq = q
     return out
+
+
+def request_keys(meta: RequestMeta) -> np.ndarray:
+    """Contents of one request: random-runs values (mean run length sqrt(n),
+    25% reversed) mapped to the request's key type (int64 keys spread over a
+    wide range; float32 keys centred on 0 with signed zeros, infinities and
+    NaNs planted)."""
+    rng = np.random.Generator(np.random.PCG64(meta.seq))
+    m = meta.n
+    vals = random_runs(rng, m, math.sqrt(m), 0.25)
+    if meta.dtype == np.int32:
+        return (vals - m // 2).astype(np.int32)
+    if meta.dtype == np.int64:
+        return (vals - m // 2).astype(np.int64) * np.int64(1 << 20)
+    return f32_from_values(rng, vals, m)
+
+
+def _request_worker(args):
+    shm_name, total_bytes, byte_off, meta = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        k = request_keys(meta)
+        buf = np.ndarray((total_bytes,), dtype=np.uint8, buffer=shm.buf)
+        buf[byte_off:byte_off + k.nbytes] = k.view(np.uint8)
+    finally:
+        shm.close()
+    return 0
+
+
+def materialize(metas: list[RequestMeta], workers: int | None = None) -> list[np.ndarray]:
+    """Keys of every request, generated in parallel worker processes."""
+    sizes = [m.n * m.dtype.itemsize for m in metas]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    total = int(offs[-1])
+    workers = workers or min(16, os.cpu_count() or 1)
+    if total < (1 << 24) or workers <= 1:
+        return [request_keys(m) for m in metas]
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=max(1, total))
+    try:
+        jobs = [(shm.name, total, int(offs[i]), metas[i]) for i in range(len(metas))]
+        with mp.get_context("fork").Pool(workers) as pool:
+            for _ in pool.imap_unordered(_request_worker, jobs, chunksize=2):
+                pass
+        big = np.ndarray((total,), dtype=np.uint8, buffer=shm.buf).copy()
+    finally:
+        shm.close()
+        shm.unlink()
+    return [big[offs[i]:offs[i + 1]].view(metas[i].dtype) for i in range(len(metas))]
+
+
+def request_trace(rate_hz: float = 2000.0, duration_s: float = 1.0, lo_exp: int = 12, hi_exp: int = 24,
+                  seed_index: int = 4, max_requests: int | None = None) -> list[Request]:
+    """Requests of trace_meta() with their contents and uint32 payloads."""
+    metas = trace_meta(rate_hz, duration_s, lo_exp, hi_exp, seed_index, max_requests)
+    keys = materialize(metas)
+    return [Request(m.arrival_s, k, payload_for(m.n)) for m, k in zip(metas, keys)]

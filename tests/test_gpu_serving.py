@@ -1,0 +1,105 @@
+"""Serving loop: every request's result equals the oracle's, the same whether
+it is served alone or batched with others, under a tight HBM budget too."""
+import numpy as np
+import pytest
+
+from paper_1805_04154_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def make_requests(metas, keys, torch):
+    from paper_1805_04154_amd import batched, serving
+    reqs = []
+    for i, (m, k) in enumerate(zip(metas, keys)):
+        reqs.append(serving.ServedRequest(i, m.arrival_s, batched.to_device(k),
+                                          batched.to_device(W.payload_for(m.n))))
+    return reqs
+
+
+def host(t, dtype):
+    import torch
+    if t.dtype == torch.uint32:
+        return t.view(torch.int32).cpu().numpy().view(np.uint32)
+    return t.cpu().numpy().view(dtype)
+
+
+@pytest.fixture(scope="module")
+def trace():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    metas = W.trace_meta(rate_hz=4000, duration_s=0.03, lo_exp=6, hi_exp=16, seed_index=11)
+    keys = W.materialize(metas, workers=1)
+    import oracle
+    refs = [oracle.powersort(k, W.payload_for(len(k))) for k in keys]
+    return metas, keys, refs
+
+
+def check(done, refs, keys):
+    assert len(done) == len(refs)
+    for r in done:
+        ref = refs[r.rid]
+        assert np.array_equal(host(r.keys, keys[r.rid].dtype).view(np.uint8), ref.keys.view(np.uint8)), r.rid
+        assert np.array_equal(host(r.payload, np.uint32), ref.payload), r.rid
+        assert r.merge_cost == ref.merge_cost, r.rid
+
+
+def test_batched_serving_matches_oracle(trace):
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    assert len({k.dtype for k in keys}) == 3
+    reqs = make_requests(metas, keys, torch)
+    srv = serving.SortServer(hbm_budget_bytes=1 << 30, slots=2)
+    done = srv.serve(reqs)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+    st = serving.latency_stats(done)
+    assert st["p50_ms"] <= st["p99_ms"]
+
+
+def test_alone_equals_in_the_mix(trace):
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    mixed = make_requests(metas, keys, torch)
+    serving.SortServer(hbm_budget_bytes=1 << 30, slots=3).serve(mixed, realtime=False)
+    torch.cuda.synchronize()
+    for i in range(0, len(metas), max(1, len(metas) // 12)):
+        alone = make_requests([metas[i]], [keys[i]], torch)
+        alone[0].rid = 0
+        serving.SortServer(hbm_budget_bytes=1 << 28, slots=1).serve(alone, realtime=False)
+        torch.cuda.synchronize()
+        m = next(r for r in mixed if r.rid == i)
+        assert torch.equal(alone[0].keys.view(torch.uint8) if alone[0].keys.dtype != torch.uint8 else alone[0].keys,
+                           m.keys.view(torch.uint8)), i
+        assert torch.equal(alone[0].payload.view(torch.int32), m.payload.view(torch.int32)), i
+        assert alone[0].merge_cost == m.merge_cost == refs[i].merge_cost
+
+
+def test_tight_budget_and_plain(trace):
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    biggest = max(m.n for m in metas)
+    reqs = make_requests(metas, keys, torch)
+    # room for one or two requests at a time: admission waits for memory
+    srv = serving.SortServer(hbm_budget_bytes=2 * 24 * biggest + (1 << 20), slots=2)
+    done = srv.serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+    reqs = make_requests(metas, keys, torch)
+    done = serving.serve_plain(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+
+
+def test_oversized_request_is_rejected(trace):
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    big = max(range(len(metas)), key=lambda i: metas[i].n)
+    reqs = make_requests([metas[big]], [keys[big]], torch)
+    srv = serving.SortServer(hbm_budget_bytes=24 * (metas[big].n // 2), slots=1)
+    with pytest.raises(ValueError):
+        srv.serve(reqs, realtime=False)
