@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -55,6 +56,40 @@ def to_dev(a: np.ndarray):
     if a.dtype == np.uint64:
         return torch.from_numpy(a.view(np.int64)).cuda().view(torch.uint64)
     return torch.from_numpy(a).cuda()
+
+
+COUNTERS_MD = os.path.join(ROOT, "profiles", "merge_pass_counters_zipf_2p28_i32.md")
+
+
+def merge_kernel_digest() -> str:
+    """Digest of the merge-pass kernel's source text (its LDS struct and body)."""
+    src = open(os.path.join(ROOT, "paper_1805_04154_amd", "csrc", "merge.hip")).read()
+    a = src.index("template <int KT, int TILE>\nstruct MergeShared")
+    a2 = src.index("\n};\n", a)
+    b = src.index("template <int KT, bool HP, int NT>\n__global__ __launch_bounds__(NT) void merge_pass_kernel")
+    b2 = src.index("\n}\n", b)
+    return hashlib.sha256((src[a:a2] + src[b:b2]).encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per merge-pass launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy), if
+    it was taken on this workload and on the current kernel source; else None."""
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("workload") != workload or fields.get("kernel_source_digest") != merge_kernel_digest():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, budget_s: float) -> dict:
@@ -120,40 +155,56 @@ def main() -> int:
 
     # Fresh copies of the input for every step, staged in HBM before timing.
     src_k, src_p = to_dev(wl.keys), to_dev(wl.payload)
-    nstep = args.warmup + args.steps
-    copies = [(src_k.clone(), src_p.clone()) for _ in range(nstep)]
+    copies = [(src_k.clone(), src_p.clone()) for _ in range(args.steps)]
     M = torch.zeros(1, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
+
+    def refill():
+        for k, p in copies:
+            k.copy_(src_k)
+            p.copy_(src_p)
+        torch.cuda.synchronize()
+
+    def region(groups):
+        """Sort every copy back to back; groups: kernel groups timed with
+        HIP events on the sort's stream (None: no events at all)."""
+        refill()
+        binding.profile_enable(groups is not None, groups=groups if groups else None)
+        binding.profile_read(reset=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        e0.record(stream)
+        for k, p in copies:
+            binding.sort(k, p, min_run=args.min_run, merge_cost=M)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        pr = binding.profile_read(reset=True) if groups is not None else None
+        binding.profile_enable(False)
+        return t_b - t_a, e0.elapsed_time(e1) / 1e3, pr
 
     for i in range(args.warmup):
-        binding.sort(copies[i][0], copies[i][1], min_run=args.min_run, merge_cost=M)
+        k, p = copies[i % len(copies)]
+        k.copy_(src_k)
+        p.copy_(src_p)
+        binding.sort(k, p, min_run=args.min_run, merge_cost=M)
     torch.cuda.synchronize()
 
-    binding.profile_enable(True)
-    binding.profile_read(reset=True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.warmup, nstep):
-        binding.sort(copies[i][0], copies[i][1], min_run=args.min_run, merge_cost=M)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = binding.profile_read(reset=True)
-    binding.profile_enable(False)
-
-    wall_s = t1 - t0
-    ev_s = ev0.elapsed_time(ev1) / 1e3
-    step_s = wall_s / args.steps
-    merge_cost = int(M.item())
-
-    # Verify the last step against properties that fix the stable sort.
+    # Timed region: every merge-pass launch carries its own dispatch events.
+    wall_s, ev_s, prof = region(("merge",))
+    # Verify the timed region's last step before anything overwrites it.
     k_out, p_out = copies[-1]
     kh = k_out.view(torch.int64 if kb == 8 else torch.int32).cpu().numpy()
     ph = p_out.view(torch.int32).cpu().numpy().view(np.uint32)
+    # Informational: the same steps without any events, and with every group timed.
+    plain_s, _, _ = region(None)
+    _, _, prof_all = region(tuple(binding.PROF_GROUPS))
+    step_s = wall_s / args.steps
+    merge_cost = int(M.item())
+
+    # Verify the timed region's last step against properties that fix the stable sort.
     okeys = wl.keys.view(np.int64 if kb == 8 else np.int32)
     sorted_ok = bool(np.all(wl.keys[ph][1:] >= wl.keys[ph][:-1]))
     seen = np.zeros(n, dtype=bool)
@@ -175,13 +226,15 @@ def main() -> int:
 
     # Roofline of the dominant kernel: the merge-path pass.  Algorithmic bytes
     # per merged output element = read both inputs + write the result.
+    # Durations: the dispatch events of every merge-pass launch of the timed
+    # region.
     mp = prof["merge"]
     mp_launch_ms = mp["ms"] / max(mp["launches"], 1)
     mp_bytes = 2 * rec_bytes * mp["elems"]
     mp_bytes_per_launch = mp_bytes / max(mp["launches"], 1)
     achieved_gbs = (mp_bytes_per_launch / (mp_launch_ms / 1e3)) / 1e9 if mp_launch_ms > 0 else 0.0
     peak_gbs = HBM_PEAK_BPS / 1e9
-    traffic = None
+    traffic = measured_traffic(wl.name) if args.min_run == 24 else None
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": peak_gbs, "unit": "GB/s",
                 "frac": round(achieved_gbs / peak_gbs, 4), "traffic": traffic,
                 "kernel": "merge_pass_kernel", "launch_ms": round(mp_launch_ms, 4),
@@ -190,9 +243,11 @@ def main() -> int:
     b_alg = rec_bytes * (2 * merge_cost + 2 * n)
     path = {"algorithmic_bytes": int(b_alg), "achieved_GBps": round(b_alg / step_s / 1e9, 1),
             "frac": round(b_alg / step_s / HBM_PEAK_BPS, 4)}
-    groups = {g: {"ms_per_step": round(prof[g]["ms"] / args.steps, 4),
-                  "launches_per_step": prof[g]["launches"] // max(args.steps, 1),
-                  "elems_per_step": prof[g]["elems"] // max(args.steps, 1)}
+    # Informational breakdown from the region with every group timed (its
+    # events add some microseconds per group, so its total is not the headline).
+    groups = {g: {"ms_per_step": round(prof_all[g]["ms"] / args.steps, 4),
+                  "launches_per_step": prof_all[g]["launches"] // max(args.steps, 1),
+                  "elems_per_step": prof_all[g]["elems"] // max(args.steps, 1)}
               for g in binding.PROF_GROUPS}
 
     out = {
@@ -215,6 +270,7 @@ def main() -> int:
         "path_roofline": path,
         "kernel_groups": groups,
         "event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
+        "ms_per_step_without_events": round(plain_s / args.steps * 1e3, 4),
         "gen_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:
@@ -296,7 +352,7 @@ def run_batched(args) -> int:
         return 1
     M = int(b.costs.cpu().numpy().view(np.uint64).sum())
     b_alg = 8 * (2 * M + 2 * n)
-    binding.profile_enable(True)
+    binding.profile_enable(True, groups=("merge",))
     binding.profile_read(reset=True)
     restore()
     torch.cuda.synchronize()

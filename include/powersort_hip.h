@@ -177,9 +177,15 @@ typedef struct {
     uint64_t elems[PS_PROF_GROUPS];
 } ps_profile;
 
-/* Turn the profiling mode on (1) or off (0) for subsequent calls of this
- * process, for tools such as benchmarks.  It adds event records between
- * launches and a few device atomics; results are unchanged. */
+/* Turn the profiling mode off (0) or on for subsequent calls of this process,
+ * for tools such as benchmarks: 1 times every group, any other value is a
+ * mask of groups to time (bit g for group g; a mask holding only group 0 is
+ * not expressible, as 1 means all).  Groups of one launch (big leaf, fused,
+ * merge, split) are timed by the start and end events of the launch's own
+ * dispatch, the others by events recorded around their launches, which
+ * costs some microseconds per group.  Element counts are kept for every
+ * group while profiling is on (a few device atomics).  Results are
+ * unchanged. */
 ps_status ps_profile_enable(int on);
 
 /* Wait for the profiled work, add it to the running totals and copy them to

@@ -244,10 +244,21 @@ def get_tuning() -> dict:
     return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
 
 
-def profile_enable(on: bool = True):
-    """Time the library's kernel groups with HIP events on the caller's stream."""
+def profile_enable(on: bool = True, groups=None):
+    """Time the library's kernel groups with HIP events on the caller's stream:
+    every group, or only the named ones (e.g. ``groups=("merge",)``)."""
     lib = load_library()
-    _check(lib.ps_profile_enable(int(on)))
+    if not on:
+        mask = 0
+    elif groups is None:
+        mask = 1
+    else:
+        mask = 0
+        for g in groups:
+            mask |= 1 << PROF_GROUPS.index(g)
+        if mask == 1:
+            raise ValueError("timing the partition group alone is not expressible; add another group")
+    _check(lib.ps_profile_enable(mask))
 
 
 def profile_read(reset: bool = False) -> dict:

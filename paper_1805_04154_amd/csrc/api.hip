@@ -225,6 +225,7 @@ struct ProfPending {
 };
 struct ProfState {
     bool on = false;
+    uint32_t mask = 0;  // groups timed with events
     std::vector<ProfPending> pending;
     std::vector<hipEvent_t> pool;
     ps_profile totals{};
@@ -253,7 +254,7 @@ struct ProfScope {
     hipStream_t st = nullptr;
     ProfScope(int g, int nl, uint64_t host_elems, hipStream_t s) : group(g), launches(nl), elems(host_elems), st(s) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (!g_prof.on) return;
+        if (!g_prof.on || !((g_prof.mask >> g) & 1)) return;
         a = prof_event();
         if (a && hipEventRecord(a, st) == hipSuccess) active = true;
     }
@@ -262,6 +263,35 @@ struct ProfScope {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         hipEvent_t b = prof_event();
         if (b && hipEventRecord(b, st) == hipSuccess) g_prof.pending.push_back({group, launches, elems, a, b});
+    }
+};
+
+// Times one launch with the start / end events of its own dispatch
+// (hipExtLaunchKernel), which adds no packets between launches.
+struct ProfLaunch {
+    int group;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit ProfLaunch(int g) : group(g) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof.on || !((g_prof.mask >> g) & 1)) return;
+        a = prof_event();
+        b = prof_event();
+        if (!a || !b) {
+            if (a) g_prof.pool.push_back(a);
+            if (b) g_prof.pool.push_back(b);
+            a = b = nullptr;
+        }
+    }
+    void done(hipError_t launched) {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (launched == hipSuccess) {
+            g_prof.pending.push_back({group, 1, 0, a, b});
+        } else {
+            g_prof.pool.push_back(a);
+            g_prof.pool.push_back(b);
+        }
+        a = b = nullptr;
     }
 };
 
@@ -428,22 +458,17 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
-        {
-            ProfScope ps_(PS_PROF_BIG_LEAF, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 0, 0, tune.grid_big_leaf, st);
-        }
-        if (e == hipSuccess) {
-            ProfScope ps_(PS_PROF_FUSED, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 1, 0, grid_fuse, st);
-        }
+        auto stage = [&](int group, int s, uint32_t p, uint32_t grid) {
+            ProfLaunch pl(group);
+            const hipError_t r = launch_move_stage(c.kt, hp, ma, s, p, grid, st, pl.a, pl.b);
+            pl.done(r);
+            return r;
+        };
+        e = stage(PS_PROF_BIG_LEAF, 0, 0, tune.grid_big_leaf);
+        if (e == hipSuccess) e = stage(PS_PROF_FUSED, 1, 0, grid_fuse);
         for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
-            {
-                ProfScope sp_(PS_PROF_SPLIT, 1, 0, st);
-                e = launch_move_stage(c.kt, hp, ma, 3, p, tune.grid_split, st);  // tile co-ranks of pass p
-            }
-            if (e != hipSuccess) break;
-            ProfScope ps_(PS_PROF_MERGE, 1, 0, st);
-            e = launch_move_stage(c.kt, hp, ma, 2, p, tune.grid_merge, st);
+            e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);  // tile co-ranks of pass p
+            if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
         if (prof_on()) {
@@ -614,6 +639,7 @@ ps_status ps_profile_enable(int on) {
         g_prof.dev = (unsigned long long*)p;
     }
     g_prof.on = on != 0;
+    g_prof.mask = (on == 1) ? ((1u << PS_PROF_GROUPS) - 1) : (uint32_t)on;
     return PS_OK;
 }
 

@@ -124,6 +124,6 @@ hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st);
 hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st);
 hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st);
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
-                             hipStream_t st);
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace ps

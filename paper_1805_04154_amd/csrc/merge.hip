@@ -18,6 +18,8 @@
 //    and their children have larger powers (Lemma "Path power
 //    monotonicity"), so passes p = pmax..1 respect every dependency.
 // Every merge is stable: on equal keys the left run goes first (App. B.1).
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "block.hpp"
 #include "internal.hpp"
@@ -495,9 +497,18 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
 
 // ------------------------------------------------------------- host launch
 
+// Plain launch, or one timed by its own dispatch events when ev0 is set.
+template <class F, class... Args>
+static void launch(F kernel, uint32_t grid, uint32_t block, uint32_t lds, hipStream_t st, hipEvent_t ev0,
+                   hipEvent_t ev1, Args... args) {
+    if (ev0) hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, st, ev0, ev1, 0, args...);
+    else hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, st, args...);
+}
+
 template <int KT, bool HP>
-static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st) {
-    if (stage == 0) hipLaunchKernelGGL((big_leaf_kernel<KT, HP>), dim3(grid), dim3(kThreads), 0, st, a);
+static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+    if (stage == 0) launch(big_leaf_kernel<KT, HP>, grid, kThreads, 0, st, ev0, ev1, a);
     else if (stage == 1) {
         const uint32_t lds = fuse_layout(sizeof(typename Key<KT>::ukey), HP, a.fuse_max_leaves).bytes;
         static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (gfx950 has 160 KiB)
@@ -506,24 +517,22 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
                                       160 * 1024);
             attr_set = true;
         }
-        hipLaunchKernelGGL((fused_kernel<KT, HP>), dim3(grid), dim3(kFuseThreads), lds, st, a);
+        launch(fused_kernel<KT, HP>, grid, kFuseThreads, lds, st, ev0, ev1, a);
     }
     else if (stage == 2) {
-        if (a.merge_tile == 2048)
-            hipLaunchKernelGGL((merge_pass_kernel<KT, HP, 256>), dim3(grid), dim3(256), 0, st, a, p);
-        else
-            hipLaunchKernelGGL((merge_pass_kernel<KT, HP, 512>), dim3(grid), dim3(512), 0, st, a, p);
+        if (a.merge_tile == 2048) launch(merge_pass_kernel<KT, HP, 256>, grid, 256, 0, st, ev0, ev1, a, p);
+        else launch(merge_pass_kernel<KT, HP, 512>, grid, 512, 0, st, ev0, ev1, a, p);
     }
-    else hipLaunchKernelGGL((split_kernel<KT>), dim3(grid), dim3(kThreads), 0, st, a, p);
+    else launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
 }
 
 // stage 0: big leaves; 1: fused subtrees; 2: the merge pass of power p;
-// 3: the split pass of power p.
+// 3: the split pass of power p.  ev0 / ev1: optional dispatch events.
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
-                             hipStream_t st) {
-#define PS_STAGE(KTV)                                                   \
-    if (hp) launch_stage_t<KTV, true>(a, stage, p, grid, st);           \
-    else launch_stage_t<KTV, false>(a, stage, p, grid, st);             \
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+#define PS_STAGE(KTV)                                                            \
+    if (hp) launch_stage_t<KTV, true>(a, stage, p, grid, st, ev0, ev1);          \
+    else launch_stage_t<KTV, false>(a, stage, p, grid, st, ev0, ev1);            \
     break
     switch (kt) {
     case KT_I32: PS_STAGE(KT_I32);
