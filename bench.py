@@ -124,7 +124,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--segments", type=int, default=4096, help="arrays in the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched: skip the autotuner")
-    ap.add_argument("--duration", type=float, default=0.25, help="served: seconds of Poisson arrivals")
+    ap.add_argument("--duration", type=float, default=1.0, help="served: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=48.0, help="served: HBM budget of the server")
     ap.add_argument("--slots", type=int, default=2, help="served: batches in flight")

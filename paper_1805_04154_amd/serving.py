@@ -37,6 +37,7 @@ class ServedRequest:
     arrival_s: float
     keys: torch.Tensor          # device, sorted in place on completion
     payload: torch.Tensor       # device uint32, permuted alongside
+    launch_s: float | None = None  # when its sort was enqueued
     done_s: float | None = None
     merge_cost: int | None = None
 
@@ -121,6 +122,8 @@ class SortServer:
             ev = torch.cuda.Event()
             ev.record(slot.stream)
         slot.batch, slot.event, slot.costs, slot.start_s = batch, ev, costs, now
+        for r in batch:
+            r.launch_s = now
 
     def _poll(self, slot: _Slot, now: float, done: list):
         if slot.event is None or not slot.event.query():
@@ -208,6 +211,7 @@ def serve_plain(requests: list[ServedRequest], min_run: int | None = None, realt
         while nxt < len(requests) and (requests[nxt].arrival_s <= now or not realtime):
             r = requests[nxt]
             M = torch.zeros(1, dtype=torch.int64, device=r.keys.device)
+            r.launch_s = now
             binding.sort(r.keys, r.payload, min_run=min_run, merge_cost=M)
             ev = torch.cuda.Event()
             ev.record(s)
@@ -228,10 +232,38 @@ def serve_plain(requests: list[ServedRequest], min_run: int | None = None, realt
     return done
 
 
-def latency_stats(done: list[ServedRequest]) -> dict:
+def busy_time(intervals: list[tuple[float, float]]) -> float:
+    """Length of the union of [start, end) intervals, e.g. (launch_s, done_s)
+    of served requests: the host-observed time with work in flight."""
+    total, cur_s, cur_e = 0.0, None, None
+    for s, e in sorted(intervals):
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                total += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        total += cur_e - cur_s
+    return total
+
+
+def algorithmic_bytes(done: list[ServedRequest]) -> int:
+    """Sum over requests of (K+V)(2M + 2n): each merge reads its inputs and
+    writes its result, plus one pass for run detection and leaf formation."""
+    return sum((KEY_BYTES[r.keys.dtype] + 4) * (2 * int(r.merge_cost) + 2 * r.n) for r in done)
+
+
+def latency_stats(done: list[ServedRequest], hbm_peak_bps: float = 8.0e12) -> dict:
+    """p50/p99/mean latency (arrival to completion), keys/s over the span, and
+    the roofline fraction of the algorithmic bytes over the busy time."""
     lat = np.array([r.done_s - r.arrival_s for r in done]) * 1e3
     keys = sum(r.n for r in done)
     span = max(r.done_s for r in done) - min(r.arrival_s for r in done)
+    busy = busy_time([(r.launch_s, r.done_s) for r in done])
+    b_alg = algorithmic_bytes(done)
     return {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
-            "keys": int(keys), "span_s": round(span, 4), "keys_per_s": round(keys / span, 1)}
+            "keys": int(keys), "span_s": round(span, 4), "keys_per_s": round(keys / span, 1),
+            "busy_s": round(busy, 4), "algorithmic_bytes": int(b_alg),
+            "busy_roofline_frac": round(b_alg / busy / hbm_peak_bps, 4) if busy > 0 else None}

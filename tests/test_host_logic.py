@@ -1,0 +1,68 @@
+"""Host-side logic that needs no GPU: the seeded generators, the serving
+statistics and the autotuner's search space."""
+import numpy as np
+import pytest
+
+from paper_1805_04154_amd import workloads as W
+
+
+def test_generators_are_deterministic():
+    a = W.runs_2p20()
+    b = W.runs_2p20()
+    assert np.array_equal(a.keys, b.keys) and np.array_equal(a.payload, b.payload)
+    assert np.array_equal(a.payload, np.arange(a.n, dtype=np.uint32))
+    z1 = W.zipf_runs(1 << 16, key_dtype=np.int32)
+    z2 = W.zipf_runs(1 << 16, key_dtype=np.uint64)
+    # the int32 headline twin holds the same values as the uint64 workload
+    assert np.array_equal(z1.keys.astype(np.uint64), z2.keys)
+    assert z1.keys.min() >= 0 and z1.keys.max() < (1 << 20)
+
+
+def test_batched_generator_does_not_depend_on_workers():
+    one = W.batched_random_runs(nseg=24, lo_exp=4, hi_exp=12, workers=1)
+    many = W.batched_random_runs(nseg=24, lo_exp=4, hi_exp=12, workers=3)
+    assert np.array_equal(one.offsets, many.offsets)
+    assert np.array_equal(one.keys, many.keys)
+    sizes = np.diff(one.offsets.astype(np.int64))
+    assert sizes.min() >= 16 and sizes.max() <= 4096
+    # every segment is a permutation of 0..size-1 (random-runs model)
+    for g in range(24):
+        seg = one.keys[int(one.offsets[g]):int(one.offsets[g + 1])]
+        assert np.array_equal(np.sort(seg), np.arange(seg.size))
+
+
+def test_request_trace_shape():
+    metas = W.trace_meta(rate_hz=2000.0, duration_s=0.05)
+    arr = np.array([m.arrival_s for m in metas])
+    assert np.all(np.diff(arr) >= 0) and arr.max() < 0.05
+    sizes = np.array([m.n for m in metas])
+    assert sizes.min() >= (1 << 12) and sizes.max() <= (1 << 24)
+    assert {m.dtype for m in metas} <= {np.dtype(np.int32), np.dtype(np.int64), np.dtype(np.float32)}
+    # about rate * duration arrivals (Poisson: 100 expected)
+    assert 60 <= len(metas) <= 140
+
+
+def test_busy_time_is_the_union_of_intervals():
+    from paper_1805_04154_amd.serving import busy_time
+    assert busy_time([]) == 0.0
+    assert busy_time([(0.0, 1.0)]) == 1.0
+    assert busy_time([(0.0, 1.0), (0.5, 2.0)]) == 2.0  # overlap counted once
+    assert busy_time([(3.0, 4.0), (0.0, 1.0)]) == 2.0  # disjoint, any order
+    assert busy_time([(0.0, 5.0), (1.0, 2.0), (6.0, 7.0)]) == 6.0  # nested
+
+
+def test_autotuner_search_space():
+    pytest.importorskip("torch")
+    from paper_1805_04154_amd import autotune
+    from paper_1805_04154_amd.binding import TUNING_FIELDS
+    full, small = autotune.candidates(), autotune.candidates(small=True)
+    for cands in (full, small):
+        keys = [tuple(sorted(c.items())) for c in cands]
+        assert len(set(keys)) == len(keys)
+        for c in cands:
+            assert set(c) <= set(TUNING_FIELDS)
+            assert c["merge_tile"] in (2048, 4096)
+            assert all(1 <= c[k] <= 65536 for k in c if k.startswith("grid_"))
+    import torch
+    assert autotune.signature(3 << 20, 4096, torch.int32, None) == autotune.signature(2 << 20, 5000, torch.int32, 24)
+    assert autotune.signature(1 << 20, 1, torch.int32, None) != autotune.signature(1 << 21, 1, torch.int32, None)
