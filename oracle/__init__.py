@@ -18,6 +18,12 @@ Parity status per function (pins live in the tests' oracle-pin suite):
   merge_order          pinned: Fig. 1 powers/tree/cost, Cartesian tree of the
                        powers, entropy bounds and an interval-DP optimum
   node_power           pinned: Fig. 1 powers and an exact-rational evaluation
+  peeksort             pinned: stable-sort output, the same leaves as
+                       powersort, Fig. 1's left (Method 1) tree and cost, the
+                       bound of Thm. "peeksort", an independent
+                       nearest-boundary formulation of the split rule
+  segmented_peeksort   pinned through peeksort (one call per segment)
+  peek_merge_order     pinned: Fig. 1 left tree, Thm. "peeksort" bound
 """
 from __future__ import annotations
 
@@ -72,6 +78,17 @@ def _load():
         lib.oracle_merge_order.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, u64p]
         lib.oracle_node_power.restype = ctypes.c_uint
         lib.oracle_node_power.argtypes = [ctypes.c_uint64] * 5
+        lib.oracle_peeksort.restype = ctypes.c_int
+        lib.oracle_peeksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        u64p, u64p]
+        lib.oracle_peek_merge_order.restype = ctypes.c_int
+        lib.oracle_peek_merge_order.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                ctypes.c_void_p, u64p]
+        lib.oracle_segmented_peeksort.restype = ctypes.c_int
+        lib.oracle_segmented_peeksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
+                                                  ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -90,13 +107,14 @@ def key_type_of(keys: np.ndarray) -> str:
 class Result:
     """Everything the oracle reports for one powersort call."""
 
-    def __init__(self, keys, payload, starts, powers, merges, merge_cost):
+    def __init__(self, keys, payload, starts, powers, merges, merge_cost, depth=None):
         self.keys = keys            # sorted keys (a new array)
         self.payload = payload      # payload permuted alongside, or None
         self.starts = starts        # uint64[r+1] run starts after min-run extension
-        self.powers = powers        # uint8[r-1] boundary powers, left to right
+        self.powers = powers        # uint8[r-1] boundary powers, left to right (powersort only)
         self.merges = merges        # uint64[r-1, 3] (lo, mid, hi) in execution order
         self.merge_cost = merge_cost
+        self.depth = depth          # uint8[r] leaf depths (peeksort only)
 
     @property
     def r(self) -> int:
@@ -167,3 +185,62 @@ def merge_order(lengths) -> tuple[np.ndarray, np.ndarray, int]:
 def node_power(s1: int, n1: int, s2: int, n2: int, n: int) -> int:
     """Def. "Node Power" for runs [s1, s1+n1) and [s2, s2+n2) of an n-array."""
     return int(_load().oracle_node_power(s1, n1, s2, n2, n))
+
+
+def peeksort(keys: np.ndarray, payload: np.ndarray | None = None, min_run: int = DEFAULT_MIN_RUN,
+             details: bool = True) -> Result:
+    """Peeksort (Alg. PeekSort) over the same leaves as powersort, on copies
+    of keys/payload.  Merges are reported in post-order; powers is None."""
+    lib = _load()
+    kt = key_type_of(keys)
+    k = np.ascontiguousarray(keys).copy()
+    p = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32).copy()
+    n = k.shape[0]
+    r = ctypes.c_uint64(0)
+    M = ctypes.c_uint64(0)
+    if details:
+        starts = np.zeros(n + 1, np.uint64)
+        merges = np.zeros((max(n, 1), 3), np.uint64)
+        depth = np.zeros(max(n, 1), np.uint8)
+    else:
+        starts = merges = depth = None
+    rc = lib.oracle_peeksort(_ptr(k), _ptr(p), n, KEY_TYPES[kt], min_run, _ptr(starts), _ptr(merges),
+                             _ptr(depth), ctypes.byref(r), ctypes.byref(M))
+    if rc != 0:
+        raise RuntimeError("oracle_peeksort failed")
+    rr = r.value
+    if details:
+        starts = starts[: rr + 1].copy()
+        merges = merges[: max(rr - 1, 0)].copy()
+        depth = depth[:rr].copy()
+    return Result(k, p, starts, None, merges, M.value, depth)
+
+
+def segmented_peeksort(keys: np.ndarray, payload: np.ndarray | None, offsets: np.ndarray,
+                       min_run: int = DEFAULT_MIN_RUN):
+    """Peeksort of each segment on its own: (keys, payload or None, costs)."""
+    lib = _load()
+    kt = key_type_of(keys)
+    k = np.ascontiguousarray(keys).copy()
+    p = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32).copy()
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nseg = off.shape[0] - 1
+    costs = np.zeros(max(nseg, 1), np.uint64)
+    rc = lib.oracle_segmented_peeksort(_ptr(k), _ptr(p), _ptr(off), nseg, KEY_TYPES[kt], min_run, _ptr(costs))
+    if rc != 0:
+        raise RuntimeError("oracle_segmented_peeksort failed")
+    return k, p, costs[:nseg].copy()
+
+
+def peek_merge_order(lengths) -> tuple[np.ndarray, np.ndarray, int]:
+    """Peeksort's merge tree for given run lengths (no data moves).
+
+    Returns (merges uint64[r-1, 3] in post-order, leaf depths uint8[r], M)."""
+    L = np.ascontiguousarray(lengths, dtype=np.uint64)
+    r = L.shape[0]
+    merges = np.zeros((max(r, 1), 3), np.uint64)
+    depth = np.zeros(max(r, 1), np.uint8)
+    M = ctypes.c_uint64(0)
+    if _load().oracle_peek_merge_order(_ptr(L), r, _ptr(merges), _ptr(depth), ctypes.byref(M)) != 0:
+        raise ValueError("run lengths must be positive")
+    return merges[: max(r - 1, 0)].copy(), depth[:r].copy(), M.value

@@ -26,6 +26,9 @@
  * merging stably, taking from the right run only when its head is strictly
  * smaller (App. B.1), and charging each merge its result size (Sec. 2.2).
  *
+ * The file also holds peeksort (Alg. PeekSort, Sec. 3.1) over the same leaves;
+ * see the section at the end.
+ *
  * Parity status: pinned (see the tests' oracle-pin suite): the output against
  * a library stable sort, the run partition against two other formulations of
  * the run convention, the powers against the paper's Fig. 1 values and an
@@ -326,4 +329,142 @@ int oracle_segmented_powersort(void *keys, uint32_t *payload, const uint64_t *of
  * the tests can evaluate the defining loop on hand-picked run lengths. */
 unsigned oracle_node_power(uint64_t s1, uint64_t n1, uint64_t s2, uint64_t n2, uint64_t n) {
     return node_power(s1, n1, s2, n2, n);
+}
+
+/* ------------------------------------------------------------------ peeksort
+ *
+ * Alg. PeekSort (Sec. 3.1) over the same leaves as above: the runs of the
+ * Sec. 2 convention, each extended to the minimum run length w (App. B.4).
+ * The recursion sees a range A[l..r] (inclusive, as in the paper) made of
+ * whole leaves, whose first leaf is A[l..e] and whose last leaf is A[s..r]:
+ *   - a single leaf (e == r) needs nothing;
+ *   - with m = l + floor((r - l) / 2): if m <= e, cut after the first leaf;
+ *     if m >= s, cut before the last leaf; otherwise take the leaf A[i..j]
+ *     that contains m and cut before it if m - i < j - m, else after it;
+ *   - sort both sides recursively, then merge them (left run first on ties).
+ * So the merges come out in post-order, each charged its result size.
+ * Parity status: pinned (Fig. 1's left tree, the bound of Thm. "peeksort",
+ * an independent nearest-boundary formulation, stable-sort output).
+ */
+typedef struct {
+    arr_t *A;                 /* NULL: merge order only */
+    unsigned char *tk;
+    uint32_t *tp;
+    const uint64_t *S;        /* leaf starts, S[r] = n */
+    ora_merge *merges;        /* optional, post-order */
+    uint8_t *depth;           /* optional leaf depths */
+    uint64_t nm, M;
+} peek_t;
+
+/* Leaf k of [a, b) with S[k] <= x < S[k+1]. */
+static uint64_t leaf_containing(const uint64_t *S, uint64_t a, uint64_t b, uint64_t x) {
+    uint64_t lo = a, hi = b;  /* invariant: S[lo] <= x < S[hi] */
+    while (hi - lo > 1) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (S[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+static void peek_rec(peek_t *P, uint64_t a, uint64_t b, unsigned d) {
+    const uint64_t *S = P->S;
+    if (b - a < 2) {                        /* one run: already sorted */
+        if (P->depth) P->depth[a] = (uint8_t)d;
+        return;
+    }
+    uint64_t l = S[a], r = S[b] - 1;        /* A[l..r] */
+    uint64_t e = S[a + 1] - 1;              /* first run A[l..e] */
+    uint64_t s = S[b - 1];                  /* last run A[s..r] */
+    uint64_t m = l + (r - l) / 2;
+    uint64_t cut;                           /* first leaf of the right part */
+    if (m <= e) {
+        cut = a + 1;
+    } else if (m >= s) {
+        cut = b - 1;
+    } else {
+        uint64_t k = leaf_containing(S, a, b, m);
+        uint64_t i = S[k], j = S[k + 1] - 1;
+        cut = (m - i < j - m) ? k : k + 1;
+    }
+    peek_rec(P, a, cut, d + 1);
+    peek_rec(P, cut, b, d + 1);
+    if (P->A) merge_runs(P->A, S[a], S[cut], S[b], P->tk, P->tp);
+    if (P->merges) { P->merges[P->nm].lo = S[a]; P->merges[P->nm].mid = S[cut]; P->merges[P->nm].hi = S[b]; }
+    P->nm++;
+    P->M += S[b] - S[a];
+}
+
+/*
+ * Sort keys[0..n) (payload alongside, may be NULL) with peeksort and minimum
+ * run length w.  Optional outputs: starts (r+1, capacity n+1), merges (r-1 in
+ * post-order, capacity n), depth (per leaf, capacity n); r_out, M_out.
+ * Returns 0, or -1 on bad arguments or allocation failure.
+ */
+int oracle_peeksort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w, uint64_t *starts,
+                    ora_merge *merges, uint8_t *depth, uint64_t *r_out, uint64_t *merge_cost_out) {
+    if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
+    arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
+    if (r_out) *r_out = 0;
+    if (merge_cost_out) *merge_cost_out = 0;
+    if (n == 0) {
+        if (starts) starts[0] = 0;
+        return 0;
+    }
+    uint64_t *S = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+    unsigned char *tk = (unsigned char *)malloc(n * A.ks);
+    uint32_t *tp = (uint32_t *)malloc(n * sizeof(uint32_t));
+    if (!S || !tk || !tp) { free(S); free(tk); free(tp); return -1; }
+    uint64_t r = 0, pos = 0;
+    while (pos < n) {                       /* the leaves, left to right */
+        S[r++] = pos;
+        pos = next_leaf(&A, pos, n, w);
+    }
+    S[r] = n;
+    peek_t P = { &A, tk, tp, S, merges, depth, 0, 0 };
+    peek_rec(&P, 0, r, 0);
+    if (starts) memcpy(starts, S, (r + 1) * sizeof(uint64_t));
+    if (r_out) *r_out = r;
+    if (merge_cost_out) *merge_cost_out = P.M;
+    free(S);
+    free(tk);
+    free(tp);
+    return 0;
+}
+
+/* Peeksort's merge order for given run lengths L[0..r) (no data): records
+ * the r-1 merges in post-order and the leaf depths; M via merge_cost_out.
+ * Returns 0, or -1 if some length is 0 or memory runs out. */
+int oracle_peek_merge_order(const uint64_t *lengths, uint64_t r, ora_merge *merges, uint8_t *depth,
+                            uint64_t *merge_cost_out) {
+    if (merge_cost_out) *merge_cost_out = 0;
+    if (r == 0) return 0;
+    uint64_t *S = (uint64_t *)malloc((r + 1) * sizeof(uint64_t));
+    if (!S) return -1;
+    S[0] = 0;
+    for (uint64_t i = 0; i < r; i++) {
+        if (lengths[i] == 0) { free(S); return -1; }
+        S[i + 1] = S[i] + lengths[i];
+    }
+    peek_t P = { NULL, NULL, NULL, S, merges, depth, 0, 0 };
+    peek_rec(&P, 0, r, 0);
+    if (merge_cost_out) *merge_cost_out = P.M;
+    free(S);
+    return 0;
+}
+
+/* Peeksort of every segment [offsets[g], offsets[g+1]) on its own;
+ * per-segment merge costs go to costs[g] (may be NULL). */
+int oracle_segmented_peeksort(void *keys, uint32_t *payload, const uint64_t *offsets, uint64_t nseg,
+                              int type, uint32_t w, uint64_t *costs) {
+    size_t ks = key_size(type);
+    for (uint64_t g = 0; g < nseg; g++) {
+        uint64_t a = offsets[g], b = offsets[g + 1];
+        uint64_t M = 0;
+        if (b < a) return -1;
+        int rc = oracle_peeksort((unsigned char *)keys + a * ks, payload ? payload + a : NULL, b - a, type, w,
+                                 NULL, NULL, NULL, NULL, &M);
+        if (rc) return rc;
+        if (costs) costs[g] = M;
+    }
+    return 0;
 }

@@ -41,11 +41,26 @@ MUTANTS = {
                            "unsigned p = node_power(S->s1, e2 - s2, s2, S->e1 - S->s1, S->n);"),
 }
 
+# Mistakes in the peeksort part, checked against the peeksort pins.
+PEEK_MUTANTS = {
+    # a tie between the two ends of the middle run goes to the left end
+    "peek_tie_to_left": ("cut = (m - i < j - m) ? k : k + 1;", "cut = (m - i <= j - m) ? k : k + 1;"),
+    # the farther end of the middle run
+    "peek_far_end": ("cut = (m - i < j - m) ? k : k + 1;", "cut = (m - i < j - m) ? k + 1 : k;"),
+    # the upper middle instead of the lower one
+    "peek_midpoint_rounding": ("uint64_t m = l + (r - l) / 2;", "uint64_t m = l + (r - l + 1) / 2;"),
+    # merge cost counts only the right part
+    "peek_merge_cost_right_only": ("P->M += S[b] - S[a];", "P->M += S[b] - S[cut];"),
+    # the right part's leaves one level too deep
+    "peek_depth_off": ("peek_rec(P, cut, b, d + 1);", "peek_rec(P, cut, b, d + 2);"),
+}
+
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS))
+@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PEEK_MUTANTS))
 def test_pins_reject_planted_mistake(tmp_path, name):
-    a, b = MUTANTS[name]
+    a, b = MUTANTS[name] if name in MUTANTS else PEEK_MUTANTS[name]
+    suite = "tests/test_oracle_pins.py" if name in MUTANTS else "tests/test_oracle_peeksort.py"
     src = open(os.path.join(ROOT, "oracle", "powersort_oracle.c")).read()
     assert a in src, "mutation site not found"
     ign = shutil.ignore_patterns("*.so", "*.tmp", "__pycache__")
@@ -53,6 +68,6 @@ def test_pins_reject_planted_mistake(tmp_path, name):
         shutil.copytree(os.path.join(ROOT, d), tmp_path / d, ignore=ign)
     (tmp_path / "oracle" / "powersort_oracle.c").write_text(src.replace(a, b))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True,
+                        suite], cwd=tmp_path, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode == 1, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
