@@ -59,13 +59,25 @@ typedef enum {
     PS_KEY_F32 = 4
 } ps_key_type;
 
+/* ps_options.flags: merge by Alg. PeekSort (Sec. 3.1) instead of powersort.
+ * The leaves are the same (runs of the Sec. 2 convention extended to the
+ * minimum run length); the merge tree is the one Alg. PeekSort's recursion
+ * builds over them (Mehlhorn's Method 1, proof of Thm. "peeksort"): a range
+ * of leaves A[l..r] with first leaf A[l..e] and last leaf A[s..r] is cut,
+ * with m = l + floor((r - l) / 2), after its first leaf if m <= e, before its
+ * last leaf if m >= s, and otherwise before the leaf A[i..j] holding m if
+ * m - i < j - m, else after it.  Every entry point takes it; the output is
+ * the same stable sort, the merge cost M (and ps_inspect's tree) are
+ * peeksort's.  For ps_inspect, powers[j] then holds depth(j) + 1 of node j. */
+#define PS_FLAG_PEEKSORT 1u
+
 /* Options; a NULL pointer means all defaults.  struct_size must be
  * sizeof(ps_options). */
 typedef struct {
     uint32_t struct_size;
     uint32_t min_run;          /* w of App. B.3/B.4; 0 = default 24 (the paper's
                                   setting); 1 = pure natural runs; at most 64 */
-    uint32_t flags;            /* reserved, must be 0 */
+    uint32_t flags;            /* 0, or PS_FLAG_PEEKSORT; other bits are rejected */
     uint32_t reserved;
     void *workspace;           /* optional caller-owned device scratch */
     uint64_t workspace_bytes;  /* its size; must be >= ps_workspace_bytes(...) */

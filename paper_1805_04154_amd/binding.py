@@ -106,10 +106,15 @@ def _check(status: int):
         raise PowersortError(status, msg)
 
 
-def _opts(min_run: int | None, workspace: torch.Tensor | None = None):
-    if min_run is None and workspace is None:
+METHODS = {"powersort": 0, "peeksort": 1}  # ps_options.flags (PS_FLAG_PEEKSORT = 1)
+
+
+def _opts(min_run: int | None, workspace: torch.Tensor | None = None, method: str = "powersort"):
+    if method not in METHODS:
+        raise ValueError(f"method must be one of {sorted(METHODS)}")
+    if min_run is None and workspace is None and method == "powersort":
         return None
-    o = PsOptions(ctypes.sizeof(PsOptions), int(min_run or 0), 0, 0, None, 0)
+    o = PsOptions(ctypes.sizeof(PsOptions), int(min_run or 0), METHODS[method], 0, None, 0)
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -138,15 +143,16 @@ def _stream(stream) -> int:
 
 
 def workspace_bytes(n_total: int, num_segments: int, dtype: torch.dtype, has_payload: bool,
-                    min_run: int | None = None) -> int:
+                    min_run: int | None = None, method: str = "powersort") -> int:
     lib = load_library()
     return int(lib.ps_workspace_bytes(n_total, num_segments, KEY_TYPES[dtype], int(has_payload),
-                                      _opts(min_run)))
+                                      _opts(min_run, None, method)))
 
 
 def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int | None = None,
-         merge_cost: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None):
-    """Stable in-place powersort of a 1-D device tensor (payload permuted alongside).
+         merge_cost: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None,
+         method: str = "powersort"):
+    """Stable in-place powersort (or peeksort) of a 1-D device tensor (payload permuted alongside).
 
     merge_cost: optional 1-element int64 device tensor that receives M (as uint64 bits)."""
     lib = load_library()
@@ -154,55 +160,58 @@ def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int |
     if payload is not None and (payload.dtype not in (torch.int32, torch.uint32) or payload.numel() != keys.numel()):
         raise ValueError("payload must be a 32-bit tensor with one entry per key")
     _check(lib.ps_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None, keys.numel(),
-                       _key_type(keys), _opts(min_run, workspace),
+                       _key_type(keys), _opts(min_run, workspace, method),
                        merge_cost.data_ptr() if merge_cost is not None else None, _stream(stream)))
     return keys, payload
 
 
 def segmented_sort(keys: torch.Tensor, payload: torch.Tensor | None, offsets: torch.Tensor,
                    min_run: int | None = None, merge_costs: torch.Tensor | None = None,
-                   status: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None):
+                   status: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None,
+                   method: str = "powersort"):
     """Sort every segment [offsets[g], offsets[g+1]) independently (offsets: int64 device tensor)."""
     lib = load_library()
     _dev_check(keys, payload, offsets, merge_costs, status)
     nseg = offsets.numel() - 1
     _check(lib.ps_segmented_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None,
                                  offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
-                                 _opts(min_run, workspace),
+                                 _opts(min_run, workspace, method),
                                  merge_costs.data_ptr() if merge_costs is not None else None,
                                  status.data_ptr() if status is not None else None, _stream(stream)))
     return keys, payload
 
 
 def merge_cost(keys: torch.Tensor, min_run: int | None = None, out: torch.Tensor | None = None,
-               stream=None) -> torch.Tensor:
-    """Merge cost M of powersort on keys (keys untouched); returns a 1-element int64 device tensor."""
+               stream=None, method: str = "powersort") -> torch.Tensor:
+    """Merge cost M of powersort (or peeksort) on keys (keys untouched); returns a 1-element int64 device tensor."""
     lib = load_library()
     _dev_check(keys)
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=keys.device)
-    _check(lib.ps_merge_cost(keys.data_ptr(), keys.numel(), _key_type(keys), _opts(min_run), out.data_ptr(),
+    _check(lib.ps_merge_cost(keys.data_ptr(), keys.numel(), _key_type(keys), _opts(min_run, None, method),
+                             out.data_ptr(),
                              _stream(stream)))
     return out
 
 
 def segmented_merge_cost(keys: torch.Tensor, offsets: torch.Tensor, min_run: int | None = None,
                          out: torch.Tensor | None = None, status: torch.Tensor | None = None,
-                         stream=None) -> torch.Tensor:
+                         stream=None, method: str = "powersort") -> torch.Tensor:
     lib = load_library()
     _dev_check(keys, offsets)
     nseg = offsets.numel() - 1
     if out is None:
         out = torch.empty(nseg, dtype=torch.int64, device=keys.device)
     _check(lib.ps_segmented_merge_cost(keys.data_ptr(), offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
-                                       _opts(min_run), out.data_ptr(),
+                                       _opts(min_run, None, method), out.data_ptr(),
                                        status.data_ptr() if status is not None else None, _stream(stream)))
     return out
 
 
 def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: int | None = None,
-            stream=None) -> dict:
-    """Leaf starts, powers, node leaf ranges and leaf depths (as device tensors, trimmed to r)."""
+            stream=None, method: str = "powersort") -> dict:
+    """Leaf starts, powers (peeksort: node depth + 1), node leaf ranges and leaf depths
+    (as device tensors, trimmed to r)."""
     lib = load_library()
     _dev_check(keys, offsets)
     n = keys.numel()
@@ -217,7 +226,7 @@ def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: in
                        r.data_ptr())
     nseg = 1 if offsets is None else offsets.numel() - 1
     _check(lib.ps_inspect(keys.data_ptr(), offsets.data_ptr() if offsets is not None else None, nseg, n,
-                          _key_type(keys), _opts(min_run), ctypes.byref(out), _stream(stream)))
+                          _key_type(keys), _opts(min_run, None, method), ctypes.byref(out), _stream(stream)))
     rr = int(r.item())
     return {"r": rr, "starts": starts[: rr + 1], "powers": powers[: rr + 1], "node_left": left[:rr],
             "node_right": right[:rr], "leaf_depth": depth[:rr]}

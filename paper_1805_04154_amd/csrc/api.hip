@@ -76,6 +76,8 @@ struct Layout {
     size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split;
     uint32_t rmax;
     uint64_t split_cap = 0;
+    size_t peek_f[2] = {0, 0};  // peeksort frontiers (ranges of one depth)
+    uint32_t peek_cap = 0;
 };
 
 static size_t take(size_t& at, size_t bytes) {
@@ -85,7 +87,7 @@ static size_t take(size_t& at, size_t bytes) {
     return here;
 }
 
-static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_t w, bool moves) {
+static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_t w, bool moves, bool peek) {
     Layout L;
     size_t at = 0;
     L.scratch_keys = moves ? take(at, N * kb) : 0;
@@ -142,6 +144,12 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
     } else {
         L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.biglist = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
         L.split = 0;
+    }
+    if (peek) {
+        // ranges of one depth are disjoint and hold >= 2 leaves each
+        L.peek_cap = L.rmax / 2 + 1;
+        L.peek_f[0] = take(at, (size_t)L.peek_cap * sizeof(PeekRange));
+        L.peek_f[1] = take(at, (size_t)L.peek_cap * sizeof(PeekRange));
     }
     L.total = take(at, 0) + 256;
     return L;
@@ -316,17 +324,20 @@ struct Call {
     int32_t* d_status;          // nullable
     ps_inspect_out* inspect;    // Mode::Inspect
     Mode mode;
+    bool peek = false;          // PS_FLAG_PEEKSORT: Alg. PeekSort's tree instead of node powers
 };
 
 static size_t key_bytes(int kt) { return (kt == KT_I64 || kt == KT_U64) ? 8 : 4; }
 
-static ps_status check_common(int kt, const ps_options* opt, uint32_t* w) {
+static ps_status check_common(int kt, const ps_options* opt, uint32_t* w, bool* peek) {
     if (kt < KT_I32 || kt > KT_F32) return fail(PS_ERR_INVALID_ARG, "unknown key type");
     *w = 24;
+    *peek = false;
     if (opt) {
         if (opt->struct_size != sizeof(ps_options)) return fail(PS_ERR_INVALID_ARG, "ps_options.struct_size mismatch");
-        if (opt->flags != 0) return fail(PS_ERR_UNSUPPORTED, "ps_options.flags must be 0");
+        if (opt->flags & ~(uint32_t)PS_FLAG_PEEKSORT) return fail(PS_ERR_UNSUPPORTED, "unknown ps_options.flags bits");
         if (opt->min_run) *w = opt->min_run;
+        *peek = (opt->flags & PS_FLAG_PEEKSORT) != 0;
     }
     if (*w > (uint32_t)kMaxMinRun) return fail(PS_ERR_UNSUPPORTED, "min_run above 64 is not supported");
     return PS_OK;
@@ -345,7 +356,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     const Tuning tune = current_tuning();
     const bool hp = moves && c.payload != nullptr;
     const size_t kb = key_bytes(c.kt);
-    const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves);
+    const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves, c.peek);
     void* ws = nullptr;
     ps_status s = get_workspace(st, L.total, opt, &ws);
     if (s != PS_OK) return s;
@@ -402,13 +413,20 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     ta.Rt = (uint32_t*)at(L.Rt);
     ta.nsize = (uint32_t*)at(L.nsize);
     ta.merge_tile = tune.merge_tile;
-    {
+    // Peeksort: every internal node sits at depth <= 2 floor(lg n) - 1, so
+    // that many + 1 levels build the whole tree (the key bound of kMaxPass).
+    const uint32_t peek_levels = std::max<uint32_t>(1, 2 * ilog2_floor(c.N));
+    if (c.peek) {
+        ProfScope ps_(PS_PROF_TREE, 1 + peek_levels, c.N, st);
+        e = launch_peek_tree(ta, (PeekRange*)at(L.peek_f[0]), (PeekRange*)at(L.peek_f[1]), L.peek_cap, peek_levels,
+                             st);
+    } else {
         ProfScope ps_(PS_PROF_TREE, 4, c.N, st);
         e = launch_tree_cost(ta, st);
     }
     if (e != hipSuccess) return hip_fail(e, "tree launch");
 
-    if (c.mode == Mode::Inspect) {
+    if (c.mode == Mode::Inspect && !c.peek) {
         e = launch_node_ranges(ta, st);
         if (e != hipSuccess) return hip_fail(e, "node-range launch");
     }
@@ -427,8 +445,8 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
             ta.prof = g_prof.dev;
         }
         {
-            ProfScope ps_(PS_PROF_LISTS, 6, c.N, st);
-            e = launch_node_ranges(ta, st);
+            ProfScope ps_(PS_PROF_LISTS, c.peek ? 5 : 6, c.N, st);
+            if (!c.peek) e = launch_node_ranges(ta, st);
             if (e == hipSuccess) e = launch_tree_lists(c.kt, ta, st);
         }
         if (e != hipSuccess) return hip_fail(e, "tree-list launch");
@@ -455,7 +473,8 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         ma.fuse_max_leaves = fuse_max_leaves(c.w);
         ma.merge_tile = tune.merge_tile;
-        const uint32_t pmax = std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
+        const uint32_t pmax = c.peek ? std::min<uint32_t>(kMaxPass, peek_levels)
+                                     : std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
         auto stage = [&](int group, int s, uint32_t p, uint32_t grid) {
@@ -501,7 +520,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
 // Degenerate inputs (n_total == 0) still report merge costs of zero and a
 // valid status, through the same small kernels.
 static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st) {
-    const Layout L = make_layout(0, c.nseg, key_bytes(c.kt), false, c.w, false);
+    const Layout L = make_layout(0, c.nseg, key_bytes(c.kt), false, c.w, false, false);
     void* ws = nullptr;
     ps_status s = get_workspace(st, L.total, opt, &ws);
     if (s != PS_OK) return s;
@@ -524,9 +543,11 @@ static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st)
 static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     g_last_error.clear();
     uint32_t w;
-    ps_status s = check_common(c.kt, opt, &w);
+    bool peek;
+    ps_status s = check_common(c.kt, opt, &w, &peek);
     if (s != PS_OK) return s;
     c.w = w;
+    c.peek = peek;
     if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^32");
     if (c.nseg == 0) return fail(PS_ERR_INVALID_ARG, "num_segments must be at least 1");
     if (c.nseg >= kMaxTotal) return fail(PS_ERR_TOO_LARGE, "too many segments");
@@ -547,9 +568,10 @@ extern "C" {
 size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
                           const ps_options* opt) {
     uint32_t w;
-    if (check_common((int)key_type, opt, &w) != PS_OK) return 0;
+    bool peek;
+    if (check_common((int)key_type, opt, &w, &peek) != PS_OK) return 0;
     if (n_total > kMaxTotal || num_segments == 0 || num_segments >= kMaxTotal) return 0;
-    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, w, true).total;
+    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, w, true, peek).total;
 }
 
 ps_status ps_sort(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_type, const ps_options* opt,

@@ -83,6 +83,12 @@ constexpr uint32_t kMergeTileMin = 2048;
 constexpr int kLeafTile = 16384;
 
 constexpr int kMaxPower = 32;  // powers are at most floor(lg n) + 1 <= 32 for n < 2^31
+// Merge-pass keys: node powers, or peeksort depth + 1.  A peeksort node at
+// depth d >= 2 covers at most half the elements of its ancestor at depth
+// d - 2, so internal nodes sit at depth <= 2 floor(lg n) - 1 and their keys
+// are <= 2 floor(lg n) <= 62 for n < 2^31; they fit the fused kernel's
+// 64-bit level mask.
+constexpr int kMaxPass = 64;
 
 // Per-call limits.
 constexpr uint64_t kMaxSegment = (1ull << 31) - 1;

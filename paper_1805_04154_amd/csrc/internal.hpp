@@ -9,11 +9,12 @@ struct Counters {
     uint32_t nunits;       // fused subtrees
     uint32_t nbigleaf;     // leaves longer than kFuse
     uint32_t nbig;         // nodes longer than kFuse
-    uint32_t pcount[kMaxPower + 1];  // big nodes per power
-    uint32_t pfill[kMaxPower + 1];
-    uint32_t pbase[kMaxPower + 1];
-    uint32_t ptiles[kMaxPower + 1];  // merge tiles per power; [0] = big-leaf tiles
-    uint32_t sbase[kMaxPower + 1];   // first split record of each power's pass
+    uint32_t pcount[kMaxPass + 1];  // big nodes per pass key (power, or peeksort depth + 1)
+    uint32_t pfill[kMaxPass + 1];
+    uint32_t pbase[kMaxPass + 1];
+    uint32_t ptiles[kMaxPass + 1];  // merge tiles per pass; [0] = big-leaf tiles
+    uint32_t sbase[kMaxPass + 1];   // first split record of each pass
+    uint32_t peek_count[kMaxPass + 1];  // peeksort: ranges of each depth
 };
 
 struct Mask2 {
@@ -121,6 +122,12 @@ enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace
 hipError_t launch_partition(int kt, const PartitionArgs& a, hipStream_t st);
 hipError_t launch_init(Counters* cnt, uint64_t* mc, uint32_t nseg, hipStream_t st);
 hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st);
+struct PeekRange {
+    uint32_t a, b, g, pad;  // leaves [a, b) of segment g
+};
+// Peeksort's tree, depths, node ranges and merge cost in `levels` launches.
+hipError_t launch_peek_tree(const TreeArgs& a, PeekRange* f0, PeekRange* f1, uint32_t cap, uint32_t levels,
+                            hipStream_t st);
 hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st);
 hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st);
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,

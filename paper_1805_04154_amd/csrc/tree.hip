@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void bucket_count_kernel(const uint8_t* _
 __global__ void bucket_base_kernel(Counters* cnt) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         uint32_t acc = 0;
-        for (int p = 0; p <= kMaxPower; ++p) {
+        for (int p = 0; p <= kMaxPass; ++p) {
             cnt->pbase[p] = acc;
             cnt->pfill[p] = 0;
             acc += cnt->pcount[p];
@@ -504,11 +504,135 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
 __global__ void pass_base_kernel(Counters* cnt) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         uint32_t acc = 0;
-        for (int p = 1; p <= kMaxPower; ++p) {
+        for (int p = 1; p <= kMaxPass; ++p) {
             cnt->sbase[p] = acc;
             acc += cnt->ptiles[p];
         }
         cnt->sbase[0] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ peeksort
+//
+// Alg. PeekSort (Sec. 3.1) builds the tree top-down: a range of whole leaves
+// A[l..r] (first leaf A[l..e], last leaf A[s..r]) with m = l + floor((r-l)/2)
+// is cut after its first leaf if m <= e, before its last leaf if m >= s, and
+// otherwise at the nearer end of the leaf A[i..j] containing m: before it if
+// m - i < j - m, else after it.  One launch per level: level d reads the
+// ranges of depth d and writes their nodes and the ranges of depth d+1.
+// Node j (the cut, between leaves j-1 and j) gets the merge-pass key
+// P[j] = d + 1, so children (deeper) merge before their parent, exactly as
+// with node powers; boundaries that are not nodes keep P = 0.
+
+// lower_bound over starts[0..n): first k with starts[k] >= v.
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t n, uint64_t v) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if ((uint64_t)a[m] < v) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// Per segment: its leaves, the root range (two or more leaves) or the
+// depth-0 single leaf, and P = 0 at the segment's first boundary.
+__global__ __launch_bounds__(kThreads) void peek_roots_kernel(const uint32_t* __restrict__ starts,
+                                                              const uint64_t* __restrict__ offsets, uint32_t nseg,
+                                                              Counters* __restrict__ cnt, PeekRange* __restrict__ F0,
+                                                              uint32_t cap, uint8_t* __restrict__ P,
+                                                              uint8_t* __restrict__ leaf_depth) {
+    __shared__ uint32_t sh[kWaves];
+    __shared__ uint32_t base_sh;
+    const uint32_t r = cnt->r;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P[r] = 0;
+    for (uint32_t g0 = blockIdx.x * kThreads; g0 < nseg; g0 += gridDim.x * kThreads) {
+        const uint32_t g = g0 + threadIdx.x;
+        uint32_t a = 0, b = 0;
+        if (g < nseg) {
+            a = lower_bound_u32(starts, r + 1, offsets[g]);
+            b = lower_bound_u32(starts, r + 1, offsets[g + 1]);
+            if (b > r) b = r;
+            if (a < b) P[a] = 0;
+            if (b - a == 1) leaf_depth[a] = 0;
+        }
+        const bool root = g < nseg && b >= a + 2;
+        const uint32_t slot = block_append(root, &cnt->peek_count[0], sh, &base_sh);
+        if (root && slot < cap) F0[slot] = PeekRange{a, b, g, 0};
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void peek_level_kernel(const uint32_t* __restrict__ starts,
+                                                              Counters* __restrict__ cnt,
+                                                              const PeekRange* __restrict__ Fin,
+                                                              PeekRange* __restrict__ Fout, uint32_t cap,
+                                                              uint32_t d, uint8_t* __restrict__ P,
+                                                              uint8_t* __restrict__ node_depth,
+                                                              uint8_t* __restrict__ leaf_depth,
+                                                              uint32_t* __restrict__ Lf, uint32_t* __restrict__ Rt,
+                                                              uint32_t* __restrict__ nsize,
+                                                              unsigned long long* __restrict__ mc) {
+    __shared__ uint32_t sh[kWaves];
+    __shared__ uint32_t base_sh;
+    const uint32_t nin = min(cnt->peek_count[d], cap);
+    for (uint32_t k0 = blockIdx.x * kThreads; k0 < nin; k0 += gridDim.x * kThreads) {
+        const uint32_t k = k0 + threadIdx.x;
+        const bool valid = k < nin;
+        uint32_t a = 0, b = 0, cut = 0, g = 0, size = 0;
+        if (valid) {
+            const PeekRange R = Fin[k];
+            a = R.a;
+            b = R.b;
+            g = R.g;
+            const uint32_t l = starts[a], r = starts[b] - 1;
+            const uint32_t e = starts[a + 1] - 1, s = starts[b - 1];
+            const uint32_t m = l + (r - l) / 2;
+            if (m <= e) {
+                cut = a + 1;
+            } else if (m >= s) {
+                cut = b - 1;
+            } else {
+                // leaf kk of (a, b) with starts[kk] <= m < starts[kk+1]
+                uint32_t lo = a, hi = b;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (starts[mid] <= m) lo = mid; else hi = mid;
+                }
+                const uint32_t i = starts[lo], j = starts[lo + 1] - 1;
+                cut = (m - i < j - m) ? lo : lo + 1;
+            }
+            size = starts[b] - l;
+            P[cut] = (uint8_t)(d + 1);
+            node_depth[cut] = (uint8_t)d;
+            Lf[cut] = a;
+            Rt[cut] = b;
+            nsize[cut] = size;
+            if (cut - a == 1) leaf_depth[a] = (uint8_t)(d + 1);
+            if (b - cut == 1) leaf_depth[cut] = (uint8_t)(d + 1);
+        }
+        // M = sum of merge result sizes, per segment: one atomic per wave for
+        // the lanes of the first active lane's segment, one per other lane
+        {
+            const uint64_t act = __ballot(valid);
+            if (act) {
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                const uint32_t gl = __shfl(g, leader);
+                const bool same = valid && g == gl;
+                unsigned long long v = same ? (unsigned long long)size : 0ull;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+                if ((int)(threadIdx.x & 63) == leader) atomicAdd(&mc[gl], v);
+                if (valid && !same) atomicAdd(&mc[g], (unsigned long long)size);
+            }
+        }
+        const uint32_t nl = valid && cut - a >= 2, nr = valid && b - cut >= 2;
+        uint32_t total;
+        const uint32_t pos = block_excl_sum(nl + nr, sh, &total);
+        if (threadIdx.x == 0) base_sh = total ? atomicAdd(&cnt->peek_count[d + 1], total) : 0u;
+        __syncthreads();
+        const uint32_t base = base_sh + pos;
+        __syncthreads();
+        if (nl && base < cap) Fout[base] = PeekRange{a, cut, g, 0};
+        if (nr && base + nl < cap) Fout[base + nl] = PeekRange{cut, b, g, 0};
     }
 }
 
@@ -567,9 +691,23 @@ hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(bucket_count_kernel, dim3(gb), dim3(kThreads), 0, st, a.P, a.cnt, a.lists);
     hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(gb), dim3(kThreads), 0, st, a.P, a.cnt, a.lists);
-    hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPower + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt,
+    hipLaunchKernelGGL(tile_scan_kernel, dim3(kMaxPass + 1), dim3(kThreads), 0, st, a.starts, a.Lf, a.Rt,
                        a.node_depth, a.cnt, a.lists, a.merge_tile);
     hipLaunchKernelGGL(pass_base_kernel, dim3(1), dim3(64), 0, st, a.cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_peek_tree(const TreeArgs& a, PeekRange* f0, PeekRange* f1, uint32_t cap, uint32_t levels,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(peek_roots_kernel, dim3(grid_for(a.nseg, 1024)), dim3(kThreads), 0, st, a.starts, a.offsets,
+                       a.nseg, a.cnt, f0, cap, a.P, a.leaf_depth);
+    const uint32_t g = grid_for(cap, 2048);
+    for (uint32_t d = 0; d < levels; ++d) {
+        PeekRange* fin = (d & 1) ? f1 : f0;
+        PeekRange* fout = (d & 1) ? f0 : f1;
+        hipLaunchKernelGGL(peek_level_kernel, dim3(g), dim3(kThreads), 0, st, a.starts, a.cnt, fin, fout, cap, d,
+                           a.P, a.node_depth, a.leaf_depth, a.Lf, a.Rt, a.nsize, (unsigned long long*)a.mc);
+    }
     return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ def test_argument_validation_without_launch(lib):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
     assert lib.ps_sort(fake, None, 10, 0, _opts(binding, min_run=65), None, None) == -5
     assert b"min_run" in lib.ps_last_error()
-    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=1), None, None) == -5
+    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=2), None, None) == -5  # unknown bit
+    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=3), None, None) == -5
     assert lib.ps_sort(fake, None, 10, 0, _opts(binding, size=8), None, None) == -1
     assert lib.ps_sort(fake, None, 10, 7, None, None, None) == -1
     assert lib.ps_sort(None, None, 10, 0, None, None, None) == -1

@@ -104,9 +104,10 @@ def test_merge_cost_bound_of_theorem(oracle_mod):
         assert M >= H * n - 1e-6 * n  # no binary merge tree beats the entropy
 
 
-def test_depth_stays_below_twice_lg_n(oracle_mod):
-    """Depth bound used to size the GPU's level loop: every leaf at depth
-    <= 2 * bit_length(n) + 1 (each two levels at least halve a range)."""
+def test_depth_stays_within_twice_lg_n(oracle_mod):
+    """The bound that sizes the GPU's level loop: a node at depth d + 2 covers
+    at most half of its ancestor at depth d, so leaves sit at depth
+    <= 2 floor(lg n) (internal nodes one less)."""
     rng = np.random.default_rng(5)
     families = [
         [2 ** i for i in range(20)],                 # geometric
@@ -116,10 +117,22 @@ def test_depth_stays_below_twice_lg_n(oracle_mod):
         list(rng.integers(1, 4, size=3000)),
         [int(x) for x in np.floor(1.6 ** np.arange(30))],
     ]
+    for t in range(3000):
+        r = int(rng.integers(2, 50))
+        kind = t % 4
+        if kind == 0:
+            L = rng.integers(1, 4, r)
+        elif kind == 1:
+            L = (2.0 ** rng.uniform(0, 12, r)).astype(np.int64) + 1
+        elif kind == 2:
+            L = np.array([1 if i % 2 else int(rng.integers(1, 5000)) for i in range(r)])
+        else:
+            L = rng.permutation(np.array([int(1.7 ** i) + 1 for i in range(r)]))
+        families.append([int(x) for x in L])
     for L in families:
         _, depth, _ = oracle_mod.peek_merge_order(L)
         n = int(sum(L))
-        assert int(depth.max()) <= 2 * n.bit_length() + 1, (L[:5], int(depth.max()))
+        assert int(depth.max()) <= 2 * (n.bit_length() - 1), (L[:5], int(depth.max()))
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.uint32, np.int64, np.uint64, np.float32])
