@@ -92,23 +92,24 @@ def measured_traffic(workload: str):
         return None
 
 
-def cpu_baseline(wl, budget_s: float) -> dict:
+def cpu_baseline(wl, budget_s: float, method: str = "powersort") -> dict:
     """The oracle as it stands, single-threaded on a host core, on a prefix
     of the workload sized to take roughly budget_s seconds."""
     import oracle
+    sort = oracle.powersort if method == "powersort" else oracle.peeksort
     n = wl.n
     m = min(n, 1 << 22)
     t = time.perf_counter()
-    oracle.powersort(wl.keys[:m], wl.payload[:m], details=False)
+    sort(wl.keys[:m], wl.payload[:m], details=False)
     dt = time.perf_counter() - t
     # grow the sample while the projected time fits the budget
     while m < n and dt * 2.2 < budget_s:
         m = min(n, 2 * m)
         t = time.perf_counter()
-        oracle.powersort(wl.keys[:m], wl.payload[:m], details=False)
+        sort(wl.keys[:m], wl.payload[:m], details=False)
         dt = time.perf_counter() - t
     return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} of the {n} keys of the same workload (payload = index), one powersort call, "
+            "sample": f"first {m} of the {n} keys of the same workload (payload = index), one {method} call, "
                       f"single thread on the host CPU ({os.cpu_count()} logical cores visible), {dt:.2f} s"}
 
 
@@ -120,6 +121,8 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--workload", choices=WORKLOADS, default="zipf_i32")
     ap.add_argument("--min-run", type=int, default=24)
+    ap.add_argument("--method", choices=("powersort", "peeksort"), default="powersort",
+                    help="merge tree: node powers (powersort) or Alg. PeekSort's top-down tree")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--segments", type=int, default=4096, help="arrays in the batched workload")
@@ -177,7 +180,7 @@ def main() -> int:
         t_a = time.perf_counter()
         e0.record(stream)
         for k, p in copies:
-            binding.sort(k, p, min_run=args.min_run, merge_cost=M)
+            binding.sort(k, p, min_run=args.min_run, merge_cost=M, method=args.method)
         e1.record(stream)
         torch.cuda.synchronize()
         t_b = time.perf_counter()
@@ -189,7 +192,7 @@ def main() -> int:
         k, p = copies[i % len(copies)]
         k.copy_(src_k)
         p.copy_(src_p)
-        binding.sort(k, p, min_run=args.min_run, merge_cost=M)
+        binding.sort(k, p, min_run=args.min_run, merge_cost=M, method=args.method)
     torch.cuda.synchronize()
 
     # Timed region: every merge-pass launch carries its own dispatch events.
@@ -234,7 +237,7 @@ def main() -> int:
     mp_bytes_per_launch = mp_bytes / max(mp["launches"], 1)
     achieved_gbs = (mp_bytes_per_launch / (mp_launch_ms / 1e3)) / 1e9 if mp_launch_ms > 0 else 0.0
     peak_gbs = HBM_PEAK_BPS / 1e9
-    traffic = measured_traffic(wl.name) if args.min_run == 24 else None
+    traffic = measured_traffic(wl.name) if (args.min_run == 24 and args.method == "powersort") else None
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": peak_gbs, "unit": "GB/s",
                 "frac": round(achieved_gbs / peak_gbs, 4), "traffic": traffic,
                 "kernel": "merge_pass_kernel", "launch_ms": round(mp_launch_ms, 4),
@@ -263,7 +266,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "int64" if kb == 8 else "int32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": n, "key": str(wl.keys.dtype), "payload": "uint32 index",
+        "config": {"workload": wl.name if args.method == "powersort" else f"{wl.name}_peeksort", "n": n,
+                   "method": args.method, "key": str(wl.keys.dtype), "payload": "uint32 index",
                    "min_run": args.min_run, "merge_cost": merge_cost, "merge_cost_per_key": round(merge_cost / n, 4),
                    "parallelism": "single GPU"},
         "roofline": roofline,
@@ -274,7 +278,7 @@ def main() -> int:
         "gen_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, args.method)
     print(json.dumps(out), flush=True)
     return 0
 
