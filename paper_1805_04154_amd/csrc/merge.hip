@@ -126,6 +126,7 @@ __host__ __device__ inline FuseLayout fuse_layout(uint32_t key_bytes, bool hp, u
     at += kFuse * key_bytes;
     L.sp = at;
     at += hp ? kFuse * 4 : 0;
+
     L.lst = at;
     at += (max_leaves + 1) * 2;
     L.nlo = at;
@@ -138,6 +139,169 @@ __host__ __device__ inline FuseLayout fuse_layout(uint32_t key_bytes, bool hp, u
     at += max_leaves;
     L.bytes = (at + 15) & ~15u;
     return L;
+}
+
+// Stable LSD radix sort of the n <= kFuse order keys sk[0..n) (payload sp
+// alongside) held in LDS, 8 bits per pass, ping-ponging with tk/tp; passes
+// whose digit is the same for every key are skipped.  Wave w ranks the
+// elements [512 w, 512 w + 512) of the current order, slot q of lane L being
+// element 512 w + 64 q + L: lanes holding the same digit find each other with
+// eight ballots, and a per-wave counter per digit carries the count from one
+// slot to the next, so ranks follow the current order (stability).  The
+// per-wave counts then become destinations by a scan over (digit, wave).
+// hist: kFuseWaves x 256 counters, rank: kFuse entries.  Returns true if the
+// result ended in tk/tp.  Block-uniform; all threads call.
+template <class U, bool HP>
+__device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uint32_t* tp, uint32_t n,
+                                                 uint16_t* hist, uint16_t* rank, uint32_t* sh,
+                                                 unsigned long long* red) {
+    constexpr int BITS = 8 * sizeof(U);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // bits in which some key differs from the first one
+    U diff = 0;
+    {
+        const U k0 = sk[0];
+        for (uint32_t x = tid; x < n; x += kFuseThreads) diff |= sk[x] ^ k0;
+        unsigned long long v = (unsigned long long)diff;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o);
+        if (tid == 0) *red = 0;
+        __syncthreads();
+        if (lane == 0 && v) atomicOr(red, v);
+        __syncthreads();
+        diff = (U)*red;
+        __syncthreads();
+    }
+    bool alt = false;
+    uint16_t* hw = hist + w * 256;
+    for (int s = 0; s < BITS; s += 8) {
+        if (((diff >> s) & (U)0xFF) == 0) continue;  // every key has the same digit
+        for (uint32_t i = lane; i < 256; i += 64) hw[i] = 0;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (int q = 0; q < kFuseItems; ++q) {
+            const uint32_t x = w * 512 + q * 64 + lane;
+            const bool valid = x < n;
+            const uint32_t d = valid ? (uint32_t)((sk[x] >> s) & (U)0xFF) : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t before = (uint32_t)__popcll(peers & lt);
+            const uint32_t base = valid ? hw[d] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            if (valid && before == 0) hw[d] = (uint16_t)(base + (uint32_t)__popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+            if (valid) rank[x] = (uint16_t)(base + before);
+        }
+        __syncthreads();
+        // hist[w][d] := elements before (digit d, wave w) in the pass's order
+        uint32_t tot = 0;
+        if (tid < 256) {
+            for (int v = 0; v < kFuseWaves; ++v) {
+                const uint32_t c = hist[v * 256 + tid];
+                hist[v * 256 + tid] = (uint16_t)tot;
+                tot += c;
+            }
+        }
+        const uint32_t dbase = block_excl_sum_w<kFuseWaves>(tid < 256 ? tot : 0u, sh, nullptr);
+        if (tid < 256) {
+            for (int v = 0; v < kFuseWaves; ++v) hist[v * 256 + tid] = (uint16_t)(hist[v * 256 + tid] + dbase);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kFuseItems; ++q) {
+            const uint32_t x = w * 512 + q * 64 + lane;
+            if (x < n) {
+                const U key = sk[x];
+                const uint32_t dst = hw[(uint32_t)((key >> s) & (U)0xFF)] + rank[x];
+                tk[dst] = key;
+                if (HP) tp[dst] = sp[x];
+            }
+        }
+        __syncthreads();
+        U* t1 = sk;
+        sk = tk;
+        tk = t1;
+        uint32_t* t2 = sp;
+        sp = tp;
+        tp = t2;
+        alt = !alt;
+    }
+    return alt;
+}
+
+// LDS of fused_radix_kernel: keys and payloads twice, the per-wave digit
+// counters, the ranks, and a 128-byte header (wave totals, a reduction word).
+__host__ __device__ constexpr uint32_t radix_lds_bytes(uint32_t key_bytes, bool hp) {
+    return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2 + kFuse * 2;
+}
+
+// Fused subtrees with many leaves (4-byte keys): every merge in a subtree is
+// stable and takes the left run first, so its result is the stable sort of
+// its original elements, which the block radix sort computes in a fixed
+// number of passes instead of one pass per tree level.
+template <int KT, bool HP>
+__global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
+    using K = Key<KT>;
+    using U = typename K::ukey;
+    using raw = typename K::raw;
+    extern __shared__ __align__(16) unsigned char rsm[];
+    uint32_t* sh = reinterpret_cast<uint32_t*>(rsm);
+    unsigned long long* red = reinterpret_cast<unsigned long long*>(rsm + 64);
+    U* sk = reinterpret_cast<U*>(rsm + 128);
+    U* tk = sk + kFuse;
+    uint32_t* sp = reinterpret_cast<uint32_t*>(tk + kFuse);
+    uint32_t* tp = sp + (HP ? kFuse : 0);
+    uint16_t* hist = reinterpret_cast<uint16_t*>(tp + (HP ? kFuse : 0));
+    uint16_t* rank = hist + kFuseWaves * 256;
+    const uint32_t nunits = a.cnt->nunits;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const UnitRec ur = a.unit_rec[u];
+        const uint32_t nleaves = ur.ub - ur.ua;
+        const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
+        if (n > (uint32_t)kFuse || n == 0 || !fuse_by_radix(sizeof(U), nleaves)) continue;
+        const raw* src = (const raw*)a.keys[0];
+        const uint32_t par = a.unit_par[u];
+        raw* dst = (raw*)a.keys[par];
+        {
+            raw kv[kFuseItems];
+            uint32_t pv[kFuseItems];
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kFuseThreads;
+                if (x < n) {
+                    kv[i] = src[lo + x];
+                    if (HP) pv[i] = a.pay[0][lo + x];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kFuseThreads;
+                if (x < n) {
+                    sk[x] = K::ord(kv[i]);
+                    if (HP) sp[x] = pv[i];
+                }
+            }
+        }
+        __syncthreads();
+        const bool alt = block_radix_sort<U, HP>(sk, sp, tk, tp, n, hist, rank, sh, red);
+        const U* ok = alt ? tk : sk;
+        const uint32_t* op = alt ? tp : sp;
+#pragma unroll
+        for (int i = 0; i < kFuseItems; ++i) {
+            const uint32_t x = tid + i * kFuseThreads;
+            if (x < n) {
+                dst[lo + x] = K::unord(ok[x]);
+                if (HP) a.pay[par][lo + x] = op[x];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <int KT, bool HP>
@@ -166,6 +330,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_kernel(MoveArgs a) {
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         const uint32_t nleaves = ub - ua, nnodes = nleaves - 1;
         if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > ML) continue;
+        if (fuse_by_radix(sizeof(U), nleaves)) continue;  // fused_radix_kernel's unit
         const raw* src = (const raw*)a.keys[0];
         const uint32_t par = a.unit_par[u];
         raw* dst = (raw*)a.keys[par];
@@ -519,6 +684,17 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         }
         launch(fused_kernel<KT, HP>, grid, kFuseThreads, lds, st, ev0, ev1, a);
     }
+    else if (stage == 4) {
+        const uint32_t kb = sizeof(typename Key<KT>::ukey);
+        if (kb != 4) return;  // only 4-byte keys take the radix path
+        static bool rattr_set = false;
+        if (!rattr_set) {
+            (void)hipFuncSetAttribute((const void*)fused_radix_kernel<KT, HP>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            rattr_set = true;
+        }
+        launch(fused_radix_kernel<KT, HP>, grid, kFuseThreads, radix_lds_bytes(kb, HP), st, ev0, ev1, a);
+    }
     else if (stage == 2) {
         if (a.merge_tile == 2048) launch(merge_pass_kernel<KT, HP, 256>, grid, 256, 0, st, ev0, ev1, a, p);
         else launch(merge_pass_kernel<KT, HP, 512>, grid, 512, 0, st, ev0, ev1, a, p);
@@ -526,8 +702,10 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
     else launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
 }
 
-// stage 0: big leaves; 1: fused subtrees; 2: the merge pass of power p;
-// 3: the split pass of power p.  ev0 / ev1: optional dispatch events.
+// stage 0: big leaves; 1: fused subtrees (level by level); 4: fused
+// subtrees by radix sort (4-byte keys, many leaves; no launch otherwise);
+// 2: the merge pass of power p; 3: the split pass of power p.  ev0 / ev1:
+// optional dispatch events.
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define PS_STAGE(KTV)                                                            \
