@@ -343,6 +343,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
     __shared__ uint32_t base_sh;
     const uint32_t r = cnt->r;
     auto size_of = [&](uint32_t j) -> uint32_t { return nsize[j]; };
+    // profiling element counts, summed per thread and added once per wave
+    unsigned long long pr_leaf = 0, pr_fused = 0, pr_merge = 0;
     for (uint32_t i0 = blockIdx.x * kThreads; i0 < r; i0 += gridDim.x * kThreads) {
         const uint32_t i = i0 + threadIdx.x;
         const bool valid = i < r;
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             const uint32_t sz = nsize[i];
             if (sz > (uint32_t)kFuse) {
                 big_node = true;
-                if (prof) atomicAdd(&prof[5], (unsigned long long)sz);
+                pr_merge += sz;
             } else {
                 const uint32_t pl = P[nlf], pr = P[nrt];
                 const uint32_t par = pl > pr ? nlf : (pr > pl ? nrt : kNone);
@@ -366,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         if (big_node) L.biglist[slot] = i;
         slot = block_append(unit_node, &cnt->nunits, sh, &base_sh);
         if (unit_node) {
-            if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[nrt] - starts[nlf]));
+            pr_fused += starts[nrt] - starts[nlf];
             L.unit_rec[slot] = UnitRec{nlf, nrt, starts[nlf], starts[nrt]};
             L.unit_par[slot] = node_depth[i] & 1;
         }
@@ -388,15 +390,28 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         }
         slot = block_append(unit_leaf, &cnt->nunits, sh, &base_sh);
         if (unit_leaf) {
-            if (prof) atomicAdd(&prof[4], (unsigned long long)(starts[i + 1] - starts[i]));
+            pr_fused += starts[i + 1] - starts[i];
             L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
             L.unit_par[slot] = leaf_depth[i] & 1;
         }
         slot = block_append(big_leaf, &cnt->nbigleaf, sh, &base_sh);
         if (big_leaf) {
-            if (prof && mode != kLeafNoop) atomicAdd(&prof[3], (unsigned long long)(starts[i + 1] - starts[i]));
+            if (mode != kLeafNoop) pr_leaf += starts[i + 1] - starts[i];
             L.bigleaf[slot] = i;
             L.bigleaf_mode[slot] = mode;
+        }
+    }
+    if (prof) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            pr_leaf += __shfl_xor(pr_leaf, o);
+            pr_fused += __shfl_xor(pr_fused, o);
+            pr_merge += __shfl_xor(pr_merge, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (pr_leaf) atomicAdd(&prof[3], pr_leaf);
+            if (pr_fused) atomicAdd(&prof[4], pr_fused);
+            if (pr_merge) atomicAdd(&prof[5], pr_merge);
         }
     }
 }
