@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E
 METRIC = "keys/s and % HBM roofline (2^28 int32+idx); batched/served vs plain; p50/p99"
-WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32", "batched", "served")
+WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32", "batched", "served", "alphabetic")
+ALPHA_METRIC = "alphabetic tree (Method 2') leaves/s: node powers, tree, depths and weighted path length"
 SERVED_METRIC = ("served sorts: p50/p99 latency and keys/s, continuous batching vs plain per-request calls "
                  "(Poisson 2000 req/s, sizes 2^12..2^24, int32/int64/float32 keys + uint32 payload)")
 BATCHED_METRIC = "batched segmented sort keys/s vs plain per-array calls (4096 arrays, log-uniform sizes 2^10..2^22)"
@@ -143,6 +144,8 @@ def main() -> int:
         return run_batched(args)
     if args.workload == "served":
         return run_served(args)
+    if args.workload == "alphabetic":
+        return run_alphabetic(args)
 
     import torch
     from paper_1805_04154_amd import binding
@@ -458,6 +461,57 @@ def run_served(args) -> int:
         "gen_s": round(t_gen, 1),
     }
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_alphabetic(args) -> int:
+    """ps_alphabetic_tree on 2^log2n leaf weights (log2n capped at 24) drawn
+    as Zipf(1.2) clipped to 2^10, i.e. heavy-tailed run lengths; timed over
+    --steps calls with the weights resident in HBM, checked against the oracle
+    (the merge order of runs of those lengths) on the last call."""
+    import torch
+    from paper_1805_04154_amd import binding, workloads as W
+    import oracle
+
+    binding.load_library()
+    r = 1 << min(args.log2n, 24)
+    rng = W.config_rng(6)
+    w_np = np.minimum(rng.zipf(1.2, size=r), 1 << 10).astype(np.int32)
+    w = torch.from_numpy(w_np).cuda()
+    out = None
+    for _ in range(args.warmup):
+        out = binding.alphabetic_tree(w)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        out = binding.alphabetic_tree(w)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    powers, merges, M = oracle.merge_order(w_np.astype(np.int64))
+    ok = int(out["status"].item()) == 0 and int(out["cost"].item()) == M and \
+        np.array_equal(out["powers"].cpu().numpy()[1:r], powers)
+    if not ok:
+        print(json.dumps({"error": "alphabetic tree differs from the oracle"}))
+        return 1
+    step = wall / args.steps
+    alg = 14 * r  # read the weight; write power, left, right, depth
+    t = time.perf_counter()
+    oracle.merge_order(w_np.astype(np.int64))
+    cpu_s = time.perf_counter() - t
+    print(json.dumps({
+        "metric": ALPHA_METRIC, "value": round(r / step, 1), "unit": "leaves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"alphabetic_zipf_r{r}", "leaves": r, "weight_sum": int(w_np.sum()),
+                   "weighted_path_length": M},
+        "path_roofline": {"algorithmic_bytes": alg, "frac": round(alg / step / HBM_PEAK_BPS, 5)},
+        "event_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 4),
+        "cpu_baseline": {"value": round(r / cpu_s, 1), "unit": "leaves/s", "cores": 1, "kind": "oracle",
+                         "sample": f"oracle merge order of the same {r} weights, single thread, {cpu_s:.2f} s"},
+    }), flush=True)
     return 0
 
 

@@ -141,6 +141,26 @@ typedef struct {
 ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_segments, uint64_t n_total,
                      ps_key_type key_type, const ps_options *opt, ps_inspect_out *out, void *stream);
 
+/* Mehlhorn's Method 2' as a standalone nearly-optimal alphabetic tree
+ * builder (App. A; Def. "Node Power"; Cor. "Cartesian tree"): for leaf
+ * weights w[0..r) (device uint32, every w_i >= 1, sum W < 2^31) with leaf
+ * probabilities w_i / W, computes the node powers, the tree they define (the
+ * min-oriented Cartesian tree of the powers) and the leaf depths, and the
+ * weighted path length sum_i depth_i * w_i, i.e. W times the search cost C
+ * of Thm. "Nearly-Optimal BSTs" (iii), C <= H + 2.  This is powersort's tree
+ * for runs of lengths w_i, without keys.  Outputs are device arrays, each
+ * nullable: d_powers (r+1 bytes; node j between leaves j-1 and j has power
+ * d_powers[j], d_powers[0] = d_powers[r] = 0), d_node_left / d_node_right
+ * (r entries; node j merges leaves [d_node_left[j], j) and [j,
+ * d_node_right[j]); entry 0 is unused), d_leaf_depth (r bytes), d_cost (one
+ * uint64), d_status (one int32: PS_OK, PS_ERR_INVALID_ARG for a zero weight,
+ * PS_ERR_TOO_LARGE for W >= 2^31; on error the outputs are those of unit
+ * weights).  num_leaves in [1, 2^28], else an error is returned with nothing
+ * enqueued.  Uses the per-stream scratch pool; asynchronous on stream. */
+ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uint8_t *d_powers,
+                             uint32_t *d_node_left, uint32_t *d_node_right, uint8_t *d_leaf_depth, uint64_t *d_cost,
+                             int32_t *d_status, void *stream);
+
 /* Launch shape of the data-movement kernels (process-wide).  Every value
  * changes only speed, never results: grids are workgroup counts of
  * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048

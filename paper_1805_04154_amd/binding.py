@@ -22,7 +22,8 @@ KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, t
 
 # Every symbol include/powersort_hip.h declares.
 EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_segmented_sort", "ps_merge_cost", "ps_segmented_merge_cost",
-           "ps_inspect", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable", "ps_profile_read", "ps_release",
+           "ps_inspect", "ps_alphabetic_tree", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable",
+           "ps_profile_read", "ps_release",
            "ps_status_string", "ps_last_error")
 TUNING_FIELDS = ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split", "merge_tile")
 PROF_GROUPS = ("partition", "tree", "lists", "big_leaf", "fused", "merge", "split")
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.ps_segmented_merge_cost.argtypes = [vp, vp, u64, u64, i32, opt, vp, vp, vp]
     lib.ps_inspect.restype = i32
     lib.ps_inspect.argtypes = [vp, vp, u64, u64, i32, opt, ctypes.POINTER(PsInspectOut), vp]
+    lib.ps_alphabetic_tree.restype = i32
+    lib.ps_alphabetic_tree.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp, vp]
     lib.ps_set_tuning.restype = i32
     lib.ps_set_tuning.argtypes = [ctypes.POINTER(PsTuning)]
     lib.ps_get_tuning.restype = i32
@@ -230,6 +233,29 @@ def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: in
     rr = int(r.item())
     return {"r": rr, "starts": starts[: rr + 1], "powers": powers[: rr + 1], "node_left": left[:rr],
             "node_right": right[:rr], "leaf_depth": depth[:rr]}
+
+
+def alphabetic_tree(weights: torch.Tensor, stream=None) -> dict:
+    """Method 2' nearly-optimal alphabetic tree for integer leaf weights (a 1-D
+    int32/uint32 device tensor, every weight >= 1, sum < 2^31): node powers,
+    node leaf ranges, leaf depths, the weighted path length and a status word
+    (device tensors)."""
+    lib = load_library()
+    _dev_check(weights)
+    if weights.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("weights must be a 32-bit integer tensor")
+    r = weights.numel()
+    dev = weights.device
+    powers = torch.zeros(r + 1, dtype=torch.uint8, device=dev)
+    left = torch.zeros(max(r, 1), dtype=torch.int32, device=dev)
+    right = torch.zeros(max(r, 1), dtype=torch.int32, device=dev)
+    depth = torch.zeros(max(r, 1), dtype=torch.uint8, device=dev)
+    cost = torch.zeros(1, dtype=torch.int64, device=dev)
+    status = torch.full((1,), 99, dtype=torch.int32, device=dev)
+    _check(lib.ps_alphabetic_tree(weights.data_ptr(), r, powers.data_ptr(), left.data_ptr(), right.data_ptr(),
+                                  depth.data_ptr(), cost.data_ptr(), status.data_ptr(), _stream(stream)))
+    return {"powers": powers, "node_left": left[:r], "node_right": right[:r], "leaf_depth": depth[:r],
+            "cost": cost, "status": status}
 
 
 def set_tuning(tuning: dict | None):

@@ -64,6 +64,94 @@ __global__ void copy_dyn_kernel(const T* __restrict__ src, T* __restrict__ dst, 
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
+// ---------------------------------------------------- alphabetic trees
+//
+// Method 2' as a standalone builder (App. A): leaf weights w[0..r) become
+// "runs" [S_i, S_i + w_i) with S_i = w_0 + ... + w_{i-1}, and the tree
+// kernels of powersort then give the node powers, the Cartesian tree of the
+// powers and the weighted depth sum.  These kernels form the S_i.
+
+constexpr uint32_t kWeightBlock = kThreads * 8;  // weights per scan block
+
+// Per-block sums of the weights; flags a zero weight.
+__global__ __launch_bounds__(kThreads) void weight_sum_kernel(const uint32_t* __restrict__ w, uint32_t r,
+                                                               uint64_t* __restrict__ bsum, uint32_t* __restrict__ flag) {
+    __shared__ uint64_t sh[kWaves];
+    const uint32_t base = blockIdx.x * kWeightBlock + threadIdx.x * 8;
+    uint64_t s = 0;
+    bool zero = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t x = base + i;
+        if (x < r) {
+            const uint32_t v = w[x];
+            s += v;
+            zero |= (v == 0);
+        }
+    }
+    if (zero) atomicOr(flag, 1u);
+    uint64_t total;
+    (void)block_excl_sum64(s, sh, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the nb block sums in one block; flags a total of 2^31 or
+// more, and publishes r, the segment [0, W) and starts[r] = W.
+__global__ __launch_bounds__(kThreads) void weight_scan_kernel(uint64_t* __restrict__ bsum, uint32_t nb, uint32_t r,
+                                                            uint32_t* __restrict__ flag, Counters* __restrict__ cnt,
+                                                            uint64_t* __restrict__ offsets,
+                                                            uint32_t* __restrict__ starts) {
+    __shared__ uint64_t sh[kWaves];
+    const uint32_t per = (nb + kThreads - 1) / kThreads;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    uint64_t s = 0;
+    for (uint32_t b = b0; b < b1; ++b) s += bsum[b];
+    uint64_t total;
+    uint64_t run = block_excl_sum64(s, sh, &total);
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint64_t v = bsum[b];
+        bsum[b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        if (total > kMaxSegment) atomicOr(flag, 2u);
+        const bool bad = (*flag != 0) || total > kMaxSegment;
+        const uint64_t W = bad ? (uint64_t)r : total;  // invalid input: unit weights
+        cnt->r = r;
+        offsets[0] = 0;
+        offsets[1] = W;
+        starts[r] = (uint32_t)W;
+    }
+}
+
+// starts[i] = sum of the weights before leaf i (unit weights if flagged).
+__global__ __launch_bounds__(kThreads) void weight_starts_kernel(const uint32_t* __restrict__ w, uint32_t r,
+                                                                  const uint64_t* __restrict__ bsum,
+                                                                  const uint32_t* __restrict__ flag,
+                                                                  uint32_t* __restrict__ starts,
+                                                                  int32_t* __restrict__ status) {
+    __shared__ uint64_t sh[kWaves];
+    const uint32_t f = *flag;
+    const uint32_t base = blockIdx.x * kWeightBlock + threadIdx.x * 8;
+    uint64_t v[8];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t x = base + i;
+        v[i] = (x < r) ? (f ? 1u : w[x]) : 0u;
+        s += v[i];
+    }
+    uint64_t run = block_excl_sum64(s, sh, nullptr) + (f ? (uint64_t)blockIdx.x * kWeightBlock : bsum[blockIdx.x]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t x = base + i;
+        if (x < r) starts[x] = (uint32_t)run;
+        run += v[i];
+    }
+    if (status && blockIdx.x == 0 && threadIdx.x == 0)
+        *status = (f & 1) ? (int32_t)PS_ERR_INVALID_ARG : (f & 2) ? (int32_t)PS_ERR_TOO_LARGE : (int32_t)PS_OK;
+}
+
 // ------------------------------------------------------------------ layout
 
 struct Layout {
@@ -560,6 +648,100 @@ static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     return run(c, opt, st);
 }
 
+// Workspace of ps_alphabetic_tree: the tree arrays for r leaves.
+struct TreeLayout {
+    size_t total = 0;
+    size_t counters, offsets, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt, nsize, bsum, flag;
+    uint32_t rmax, nb;
+};
+
+static TreeLayout make_tree_layout(uint64_t r) {
+    TreeLayout L;
+    size_t at = 0;
+    L.rmax = (uint32_t)r + 1;
+    const size_t r1 = (size_t)L.rmax + 1;
+    const size_t nbm = (L.rmax + kMaskBlockA - 1) / kMaskBlockA + 1;
+    L.nb = (uint32_t)((r + kWeightBlock - 1) / kWeightBlock);
+    L.counters = take(at, kCountersBytes);
+    L.offsets = take(at, 2 * 8);
+    L.starts = take(at, r1 * 4);
+    L.Q = take(at, r1 * 8);
+    L.P = take(at, r1 + 1);
+    L.leaf_depth = take(at, r1);
+    L.node_depth = take(at, r1);
+    L.aggF = take(at, nbm * 16);
+    L.aggB = take(at, nbm * 16);
+    L.inF = take(at, nbm * 8);
+    L.inB = take(at, nbm * 8);
+    L.mc = take(at, 2 * 8);
+    L.Lf = take(at, r1 * 4);
+    L.Rt = take(at, r1 * 4);
+    L.nsize = take(at, r1 * 4);
+    L.bsum = take(at, ((size_t)L.nb + 1) * 8);
+    L.flag = take(at, 4);
+    L.total = take(at, 0) + 256;
+    return L;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+static ps_status alphabetic_tree(const uint32_t* w, uint64_t r, uint8_t* powers, uint32_t* left, uint32_t* right,
+                                 uint8_t* depth, uint64_t* cost, int32_t* status, hipStream_t st) {
+    const TreeLayout L = make_tree_layout(r);
+    void* ws = nullptr;
+    ps_status s = get_workspace(st, L.total, nullptr, &ws);
+    if (s != PS_OK) return s;
+    char* base = (char*)ws;
+    auto at = [&](size_t off) { return (void*)(base + off); };
+    Counters* cnt = (Counters*)at(L.counters);
+    uint64_t* mc = (uint64_t*)at(L.mc);
+    uint64_t* offsets = (uint64_t*)at(L.offsets);
+    uint32_t* starts = (uint32_t*)at(L.starts);
+    uint64_t* bsum = (uint64_t*)at(L.bsum);
+    uint32_t* flag = (uint32_t*)at(L.flag);
+    const uint32_t r32 = (uint32_t)r;
+    hipError_t e = launch_init(cnt, mc, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, flag);
+    hipLaunchKernelGGL(weight_sum_kernel, dim3(L.nb), dim3(kThreads), 0, st, w, r32, bsum, flag);
+    hipLaunchKernelGGL(weight_scan_kernel, dim3(1), dim3(kThreads), 0, st, bsum, L.nb, r32, flag, cnt, offsets,
+                       starts);
+    hipLaunchKernelGGL(weight_starts_kernel, dim3(L.nb), dim3(kThreads), 0, st, w, r32, bsum, flag, starts, status);
+    TreeArgs ta{};
+    ta.offsets = offsets;
+    ta.nseg = 1;
+    ta.rmax = L.rmax;
+    ta.starts = starts;
+    ta.cnt = cnt;
+    ta.Q = (uint64_t*)at(L.Q);
+    ta.P = (uint8_t*)at(L.P);
+    ta.leaf_depth = (uint8_t*)at(L.leaf_depth);
+    ta.node_depth = (uint8_t*)at(L.node_depth);
+    ta.aggF = (Mask2*)at(L.aggF);
+    ta.aggB = (Mask2*)at(L.aggB);
+    ta.inF = (uint64_t*)at(L.inF);
+    ta.inB = (uint64_t*)at(L.inB);
+    ta.mc = mc;
+    ta.Lf = (uint32_t*)at(L.Lf);
+    ta.Rt = (uint32_t*)at(L.Rt);
+    ta.nsize = (uint32_t*)at(L.nsize);
+    e = launch_tree_cost(ta, st);
+    if (e == hipSuccess && (left || right)) e = launch_node_ranges(ta, st);
+    if (e != hipSuccess) return hip_fail(e, "tree launch");
+    const uint32_t* r_dev = (const uint32_t*)cnt;
+    const dim3 g(1024), b(kThreads);
+    if (powers) hipLaunchKernelGGL(copy_dyn_kernel<uint8_t>, g, b, 0, st, ta.P, powers, r_dev, 1u, r32 + 1);
+    if (left) hipLaunchKernelGGL(copy_dyn_kernel<uint32_t>, g, b, 0, st, ta.Lf, left, r_dev, 0u, r32);
+    if (right) hipLaunchKernelGGL(copy_dyn_kernel<uint32_t>, g, b, 0, st, ta.Rt, right, r_dev, 0u, r32);
+    if (depth) hipLaunchKernelGGL(copy_dyn_kernel<uint8_t>, g, b, 0, st, ta.leaf_depth, depth, r_dev, 0u, r32);
+    if (cost) hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(64), 0, st, mc, cost, 1u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return PS_OK;
+}
+
 }  // namespace ps
 
 using namespace ps;
@@ -573,6 +755,17 @@ size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type k
     if (check_common((int)key_type, opt, &w, &peek) != PS_OK) return 0;
     if (n_total > kMaxTotal || num_segments == 0 || num_segments >= kMaxTotal) return 0;
     return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, w, true, peek).total;
+}
+
+ps_status ps_alphabetic_tree(const uint32_t* d_weights, uint64_t num_leaves, uint8_t* d_powers,
+                             uint32_t* d_node_left, uint32_t* d_node_right, uint8_t* d_leaf_depth, uint64_t* d_cost,
+                             int32_t* d_status, void* stream) {
+    g_last_error.clear();
+    if (num_leaves == 0) return fail(PS_ERR_INVALID_ARG, "num_leaves must be at least 1");
+    if (num_leaves > kMaxTreeLeaves) return fail(PS_ERR_TOO_LARGE, "num_leaves above 2^28");
+    if (!d_weights) return fail(PS_ERR_INVALID_ARG, "d_weights is NULL");
+    return alphabetic_tree(d_weights, num_leaves, d_powers, d_node_left, d_node_right, d_leaf_depth, d_cost, d_status,
+                           (hipStream_t)stream);
 }
 
 ps_status ps_sort(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_type, const ps_options* opt,

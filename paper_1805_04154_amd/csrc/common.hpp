@@ -99,6 +99,7 @@ constexpr int kMaxPass = 64;
 // Per-call limits.
 constexpr uint64_t kMaxSegment = (1ull << 31) - 1;
 constexpr uint64_t kMaxTotal = 0xFFFFFFFFull;
+constexpr uint64_t kMaxTreeLeaves = 1ull << 28;  // leaves of ps_alphabetic_tree
 
 __device__ __forceinline__ int clz32(uint32_t x) { return __clz(x); }
 

@@ -55,6 +55,9 @@ def test_argument_validation_without_launch(lib):
     assert lib.ps_merge_cost(fake, 10, 0, None, None, None) == -1
     assert lib.ps_segmented_merge_cost(fake, fake, 2, 10, 0, None, None, None, None) == -1
     assert lib.ps_inspect(fake, None, 1, 10, 0, None, None, None) == -1
+    assert lib.ps_alphabetic_tree(fake, 0, None, None, None, None, None, None, None) == -1
+    assert lib.ps_alphabetic_tree(fake, (1 << 28) + 1, None, None, None, None, None, None, None) == -2
+    assert lib.ps_alphabetic_tree(None, 5, None, None, None, None, None, None, None) == -1
 
 
 def test_status_strings(lib):
