@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E
 METRIC = "keys/s and % HBM roofline (2^28 int32+idx); batched/served vs plain; p50/p99"
-WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32", "batched", "served", "alphabetic")
+WORKLOADS = ("zipf_i32", "zipf_u64", "perm_i32", "runs_i32", "batched", "served", "alphabetic", "mergecost")
+MERGECOST_METRIC = ("merge cost M/n of powersort and peeksort (GPU ps_merge_cost) against the entropy bound and "
+                    "non-adaptive mergesort, per input family; merge-cost keys/s")
 ALPHA_METRIC = "alphabetic tree (Method 2') leaves/s: node powers, tree, depths and weighted path length"
 SERVED_METRIC = ("served sorts: p50/p99 latency and keys/s, continuous batching vs plain per-request calls "
                  "(Poisson 2000 req/s, sizes 2^12..2^24, int32/int64/float32 keys + uint32 payload)")
@@ -146,6 +148,8 @@ def main() -> int:
         return run_served(args)
     if args.workload == "alphabetic":
         return run_alphabetic(args)
+    if args.workload == "mergecost":
+        return run_mergecost(args)
 
     import torch
     from paper_1805_04154_amd import binding
@@ -466,7 +470,8 @@ def run_served(args) -> int:
 
 def run_alphabetic(args) -> int:
     """ps_alphabetic_tree on 2^log2n leaf weights (log2n capped at 24) drawn
-    as Zipf(1.2) clipped to 2^10, i.e. heavy-tailed run lengths; timed over
+    as Zipf(1.2) clipped to 2^7 (heavy-tailed run lengths whose sum stays below
+    2^31 at 2^24 leaves); timed over
     --steps calls with the weights resident in HBM, checked against the oracle
     (the merge order of runs of those lengths) on the last call."""
     import torch
@@ -476,7 +481,7 @@ def run_alphabetic(args) -> int:
     binding.load_library()
     r = 1 << min(args.log2n, 24)
     rng = W.config_rng(6)
-    w_np = np.minimum(rng.zipf(1.2, size=r), 1 << 10).astype(np.int32)
+    w_np = np.minimum(rng.zipf(1.2, size=r), 1 << 7).astype(np.int32)
     w = torch.from_numpy(w_np).cuda()
     out = None
     for _ in range(args.warmup):
@@ -511,6 +516,90 @@ def run_alphabetic(args) -> int:
         "event_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 4),
         "cpu_baseline": {"value": round(r / cpu_s, 1), "unit": "leaves/s", "cores": 1, "kind": "oracle",
                          "sample": f"oracle merge order of the same {r} weights, single thread, {cpu_s:.2f} s"},
+    }), flush=True)
+    return 0
+
+
+def topdown_merge_cost(n: int, w: int) -> int:
+    """Merge cost of non-adaptive top-down mergesort that insertion-sorts
+    subarrays of at most w elements: n + M(floor(n/2)) + M(ceil(n/2))."""
+    memo = {}
+
+    def m(k):
+        if k <= w:
+            return 0
+        if k not in memo:
+            memo[k] = k + m(k // 2) + m(k - k // 2)
+        return memo[k]
+    return m(n)
+
+
+def bottomup_merge_cost(n: int, w: int) -> int:
+    """Merge cost of non-adaptive bottom-up mergesort over blocks of w
+    elements, merging neighbours level by level (an odd block passes up)."""
+    runs = [w] * (n // w) + ([n % w] if n % w else [])
+    M = 0
+    while len(runs) > 1:
+        nxt = []
+        for i in range(0, len(runs) - 1, 2):
+            nxt.append(runs[i] + runs[i + 1])
+            M += runs[i] + runs[i + 1]
+        if len(runs) % 2:
+            nxt.append(runs[-1])
+        runs = nxt
+    return M
+
+
+def run_mergecost(args) -> int:
+    """Sec. 4's inputs as merge-cost experiments: for each family the GPU
+    computes powersort's and peeksort's merge cost M (ps_merge_cost, keys
+    untouched) and the leaf partition (ps_inspect), from which the entropy H
+    of the leaf lengths follows; M/n is compared with H, H + 2 (the bounds of
+    Thm. "powersort" / "peeksort") and with non-adaptive mergesort."""
+    import torch
+    from paper_1805_04154_amd import binding, workloads as W
+
+    binding.load_library()
+    w = args.min_run
+    n24 = 1 << 24
+    fams = [
+        ("permutation_2p24", lambda: W.random_permutation(W.make_rng(41), n24)),
+        ("random_runs_mean_sqrt_n_2p24", lambda: W.random_runs(W.make_rng(42), n24, math.sqrt(n24), 0.0)),
+        ("random_runs_mean_3000_n1e7", lambda: W.random_runs(W.make_rng(0), 10 ** 7, 3000.0, 0.0)),
+        ("random_runs_mean_64_2p24", lambda: W.random_runs(W.make_rng(43), n24, 64.0, 0.25)),
+        ("zipf_runs_2p24", lambda: W.zipf_runs(n24, key_dtype=np.int32).keys),
+    ]
+    rows = []
+    total_keys, total_s = 0, 0.0
+    for name, gen in fams:
+        keys = torch.from_numpy(np.ascontiguousarray(gen()).astype(np.int32)).cuda()
+        n = keys.numel()
+        res = {"family": name, "n": n}
+        for method in ("powersort", "peeksort"):
+            binding.merge_cost(keys, min_run=w, method=method)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                M = binding.merge_cost(keys, min_run=w, method=method)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / args.steps
+            res[f"M_over_n_{method}"] = round(int(M.item()) / n, 4)
+            res[f"ms_{method}"] = round(dt * 1e3, 4)
+            total_keys += n
+            total_s += dt
+        ins = binding.inspect(keys, min_run=w)
+        torch.cuda.synchronize()
+        L = np.diff(ins["starts"].cpu().numpy().astype(np.int64)).astype(np.float64)
+        H = float(np.sum((L / n) * np.log2(n / L)))
+        res.update({"leaves": int(ins["r"]), "H": round(H, 4), "H_plus_2": round(H + 2, 4),
+                    "topdown_mergesort": round(topdown_merge_cost(n, w) / n, 4),
+                    "bottomup_mergesort": round(bottomup_merge_cost(n, w) / n, 4)})
+        rows.append(res)
+    print(json.dumps({
+        "metric": MERGECOST_METRIC, "value": round(total_keys / total_s, 1), "unit": "keys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(total_s * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "mergecost_families", "min_run": w}, "families": rows,
     }), flush=True)
     return 0
 
