@@ -36,11 +36,11 @@ struct PartShared {
     union {
         U keys[kPairCap + 1];                 // window keys, position T0-1+k at index k
         struct {
-            uint16_t nx[2][kPartTile];        // successor (or exit) per tile position
-            uint16_t ct[2][kPartTile];        // leaf starts up to the exit
+            uint16_t nx[kPartTile];           // successor (or exit) per tile position
+            uint16_t ct[kPartTile];           // leaf starts up to the exit
         } pj;
         struct {
-            uint16_t nx[2][kPartTile];
+            uint16_t nx[kPartTile];
             uint8_t mk[kPartTile];            // chain-point marks
         } em;
     } u;
@@ -53,7 +53,7 @@ struct PartShared {
 
 // Computes, for every position s of tile [T0, T1), the encoded successor
 // J(s): a tile-local index if J(s) < T1, else kExitBit | exit code.  The
-// result is left in sm.u.pj.nx[0] (aliased by sm.u.em.nx[0]); sm.x0 receives
+// result is left in sm.u.pj.nx (aliased by sm.u.em.nx); sm.x0 receives
 // the end of the natural run crossing T0 (kInf if none, kFar if beyond the
 // window).  Returns true, without filling nx, when the whole tile lies
 // inside one natural run that extends past the window: then every J(s) is
@@ -183,7 +183,7 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
         uint16_t enc;
         if (J < T1) enc = (uint16_t)(J - T0);
         else enc = kExitBit | (uint16_t)((J != kFar && J - T1 < w) ? (J - T1) : w);
-        sm.u.pj.nx[0][s - T0] = enc;
+        sm.u.pj.nx[s - T0] = enc;
     }
     __syncthreads();
     return false;
@@ -212,24 +212,38 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
         return;
     }
 
-    // Pointer jumping to the exits, counting visited positions.
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.pj.ct[0][i] = 1;
+    // Pointer jumping to the exits, counting visited positions.  One buffer:
+    // each round reads every position's next state into registers, waits,
+    // then writes them back.
+    constexpr int kPJ = kPartTile / kThreads;  // positions per thread
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.pj.ct[i] = 1;
     __syncthreads();
-    int cur = 0;
     for (int round = 0; round < 16; ++round) {
         int any = 0;
-        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
-            const uint16_t a = sm.u.pj.nx[cur][i];
-            uint16_t na = a, nc = sm.u.pj.ct[cur][i];
-            if (!(a & kExitBit)) {
-                na = sm.u.pj.nx[cur][a];
-                nc = (uint16_t)(nc + sm.u.pj.ct[cur][a]);
-                any |= !(na & kExitBit);
+        uint16_t na[kPJ], nc[kPJ];
+#pragma unroll
+        for (int q = 0; q < kPJ; ++q) {
+            const uint32_t i = threadIdx.x + q * kThreads;
+            if (i < len) {
+                const uint16_t a = sm.u.pj.nx[i];
+                na[q] = a;
+                nc[q] = sm.u.pj.ct[i];
+                if (!(a & kExitBit)) {
+                    na[q] = sm.u.pj.nx[a];
+                    nc[q] = (uint16_t)(nc[q] + sm.u.pj.ct[a]);
+                    any |= !(na[q] & kExitBit);
+                }
             }
-            sm.u.pj.nx[cur ^ 1][i] = na;
-            sm.u.pj.ct[cur ^ 1][i] = nc;
         }
-        cur ^= 1;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPJ; ++q) {
+            const uint32_t i = threadIdx.x + q * kThreads;
+            if (i < len) {
+                sm.u.pj.nx[i] = na[q];
+                sm.u.pj.ct[i] = nc[q];
+            }
+        }
         if (!__syncthreads_or(any)) break;
     }
 
@@ -251,9 +265,9 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
             code = (uint8_t)((pos != kFar && pos - T1 < w) ? (pos - T1) : w);
             cnt = 0;
         } else {
-            const uint16_t e = sm.u.pj.nx[cur][pos - T0];
+            const uint16_t e = sm.u.pj.nx[pos - T0];
             code = (uint8_t)(e & 0xFF);
-            cnt = sm.u.pj.ct[cur][pos - T0];
+            cnt = sm.u.pj.ct[pos - T0];
         }
         tcode[(size_t)blockIdx.x * W1 + c] = code;
         tcnt[(size_t)blockIdx.x * W1 + c] = cnt;
@@ -363,24 +377,32 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
     for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.em.mk[i] = (i == pos - T0);
     __syncthreads();
-    int cur = 0;
+    constexpr int kPJ = kPartTile / kThreads;  // positions per thread
     for (int round = 0; round < 16; ++round) {
-        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
-            const uint16_t a = sm.u.em.nx[cur][i];
-            if (sm.u.em.mk[i] && !(a & kExitBit)) sm.u.em.mk[a] = 1;
+        // Mark the images of marked positions and read the doubled pointers;
+        // a mark set during this phase and seen by another thread only adds
+        // further points of the same chain.
+        int any = 0;
+        uint16_t na[kPJ];
+#pragma unroll
+        for (int q = 0; q < kPJ; ++q) {
+            const uint32_t i = threadIdx.x + q * kThreads;
+            if (i < len) {
+                const uint16_t a = sm.u.em.nx[i];
+                na[q] = a;
+                if (!(a & kExitBit)) {
+                    if (sm.u.em.mk[i]) sm.u.em.mk[a] = 1;
+                    na[q] = sm.u.em.nx[a];
+                    any |= !(na[q] & kExitBit);
+                }
+            }
         }
         __syncthreads();
-        int any = 0;
-        for (uint32_t i = threadIdx.x; i < len; i += kThreads) {
-            const uint16_t a = sm.u.em.nx[cur][i];
-            uint16_t na = a;
-            if (!(a & kExitBit)) {
-                na = sm.u.em.nx[cur][a];
-                any |= !(na & kExitBit);
-            }
-            sm.u.em.nx[cur ^ 1][i] = na;
+#pragma unroll
+        for (int q = 0; q < kPJ; ++q) {
+            const uint32_t i = threadIdx.x + q * kThreads;
+            if (i < len) sm.u.em.nx[i] = na[q];
         }
-        cur ^= 1;
         // Once J^(2^(round+1)) leaves the tile from every position, the chain
         // from the entry has at most 2^(round+1) points, all marked by now.
         if (!__syncthreads_or(any)) break;
