@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__
 template <int KT, bool HP>
 __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
     using raw = typename Key<KT>::raw;
-    constexpr int kB = 8;  // elements per thread in flight
+    constexpr int kB = 16;  // elements per thread in flight
     const uint32_t ntiles = a.cnt->ptiles[0];
     const uint32_t nleaf = a.cnt->nbigleaf;
     raw* k0 = (raw*)a.keys[0];
