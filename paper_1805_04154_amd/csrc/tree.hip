@@ -693,7 +693,8 @@ hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
-    const uint32_t gl = grid_for(a.rmax, 4096);
+    // fewer blocks: each block_append is one atomic per block on a shared counter
+    const uint32_t gl = grid_for(a.rmax, 1024);
     switch (kt) {
     case KT_I32: launch_classify_t<KT_I32>(a, gl, st); break;
     case KT_U32: launch_classify_t<KT_U32>(a, gl, st); break;
