@@ -24,6 +24,10 @@ Parity status per function (pins live in the tests' oracle-pin suite):
                        nearest-boundary formulation of the split rule
   segmented_peeksort   pinned through peeksort (one call per segment)
   peek_merge_order     pinned: Fig. 1 left tree, Thm. "peeksort" bound
+  Result.comparisons   pinned: exact counts on sorted / reversed / two-run
+                       inputs, n - 1 for run detection plus at most size - 1
+                       per merge, and the comparison bounds of Thm.
+                       "powersort" and "peeksort"
 """
 from __future__ import annotations
 
@@ -85,6 +89,8 @@ def _load():
         lib.oracle_peek_merge_order.restype = ctypes.c_int
         lib.oracle_peek_merge_order.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                                 ctypes.c_void_p, u64p]
+        lib.oracle_last_comparisons.restype = ctypes.c_uint64
+        lib.oracle_last_comparisons.argtypes = []
         lib.oracle_segmented_peeksort.restype = ctypes.c_int
         lib.oracle_segmented_peeksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
@@ -107,7 +113,7 @@ def key_type_of(keys: np.ndarray) -> str:
 class Result:
     """Everything the oracle reports for one powersort call."""
 
-    def __init__(self, keys, payload, starts, powers, merges, merge_cost, depth=None):
+    def __init__(self, keys, payload, starts, powers, merges, merge_cost, depth=None, comparisons=None):
         self.keys = keys            # sorted keys (a new array)
         self.payload = payload      # payload permuted alongside, or None
         self.starts = starts        # uint64[r+1] run starts after min-run extension
@@ -115,6 +121,7 @@ class Result:
         self.merges = merges        # uint64[r-1, 3] (lo, mid, hi) in execution order
         self.merge_cost = merge_cost
         self.depth = depth          # uint8[r] leaf depths (peeksort only)
+        self.comparisons = comparisons  # key comparisons made by the call
 
     @property
     def r(self) -> int:
@@ -146,7 +153,7 @@ def powersort(keys: np.ndarray, payload: np.ndarray | None = None, min_run: int 
         starts = starts[: rr + 1].copy()
         powers = powers[: max(rr - 1, 0)].copy()
         merges = merges[: max(rr - 1, 0)].copy()
-    return Result(k, p, starts, powers, merges, M.value)
+    return Result(k, p, starts, powers, merges, M.value, comparisons=int(lib.oracle_last_comparisons()))
 
 
 def segmented_powersort(keys: np.ndarray, payload: np.ndarray | None, offsets: np.ndarray,
@@ -213,7 +220,7 @@ def peeksort(keys: np.ndarray, payload: np.ndarray | None = None, min_run: int =
         starts = starts[: rr + 1].copy()
         merges = merges[: max(rr - 1, 0)].copy()
         depth = depth[:rr].copy()
-    return Result(k, p, starts, None, merges, M.value, depth)
+    return Result(k, p, starts, None, merges, M.value, depth, comparisons=int(lib.oracle_last_comparisons()))
 
 
 def segmented_peeksort(keys: np.ndarray, payload: np.ndarray | None, offsets: np.ndarray,

@@ -63,8 +63,14 @@ static int f32_total_less(uint32_t a, uint32_t b) {
     return a > b;                 /* both negative: larger magnitude, smaller value */
 }
 
+/* Key comparisons made by the last oracle_powersort / oracle_peeksort call
+ * (Thm. "powersort" / "peeksort" bound them); every comparison goes through
+ * key_less.  The oracle is single-threaded. */
+static uint64_t g_comparisons;
+
 /* key_less(x, y): the key stored at x orders strictly before the key at y. */
 static int key_less(const arr_t *A, const unsigned char *x, const unsigned char *y) {
+    g_comparisons++;
     switch (A->type) {
     case ORK_I32: { int32_t a, b; memcpy(&a, x, 4); memcpy(&b, y, 4); return a < b; }
     case ORK_U32: { uint32_t a, b; memcpy(&a, x, 4); memcpy(&b, y, 4); return a < b; }
@@ -99,9 +105,11 @@ static void reverse_range(arr_t *A, uint64_t s, uint64_t e) {
 static uint64_t extend_run_right(arr_t *A, uint64_t s, uint64_t n) {
     uint64_t e = s + 1;
     if (e < n && less_at(A, e, e - 1)) {
+        e++;  /* each adjacent pair is compared once */
         while (e < n && less_at(A, e, e - 1)) e++;
         reverse_range(A, s, e);
-    } else {
+    } else if (e < n) {
+        e++;
         while (e < n && !less_at(A, e, e - 1)) e++;
     }
     return e;
@@ -244,6 +252,7 @@ int oracle_powersort(void *keys, uint32_t *payload, uint64_t n, int type, uint32
                      uint64_t *r_out, uint64_t *merge_cost_out) {
     if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
     arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
+    g_comparisons = 0;
     sched_t S;
     uint64_t r = 0;
     memset(&S, 0, sizeof S);
@@ -404,6 +413,7 @@ int oracle_peeksort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_
                     ora_merge *merges, uint8_t *depth, uint64_t *r_out, uint64_t *merge_cost_out) {
     if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
     arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
+    g_comparisons = 0;
     if (r_out) *r_out = 0;
     if (merge_cost_out) *merge_cost_out = 0;
     if (n == 0) {
@@ -467,4 +477,10 @@ int oracle_segmented_peeksort(void *keys, uint32_t *payload, const uint64_t *off
         if (costs) costs[g] = M;
     }
     return 0;
+}
+
+/* Key comparisons made by the most recent oracle_powersort or
+ * oracle_peeksort call: run detection, min-run insertion sorts and merges. */
+uint64_t oracle_last_comparisons(void) {
+    return g_comparisons;
 }

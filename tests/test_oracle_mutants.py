@@ -17,8 +17,8 @@ MUTANTS = {
     "unstable_merge": ("int take_right = (i >= mid) || (j < hi && less_at(A, j, i));",
                        "int take_right = (i >= mid) || (j < hi && !less_at(A, i, j));"),
     # weakly (not strictly) decreasing runs are reversed
-    "nonstrict_descending_run": ("if (e < n && less_at(A, e, e - 1)) {\n        while (e < n && less_at(A, e, e - 1)) e++;",
-                                 "if (e < n && !less_at(A, e - 1, e)) {\n        while (e < n && !less_at(A, e - 1, e)) e++;"),
+    "nonstrict_descending_run": ("if (e < n && less_at(A, e, e - 1)) {\n        e++;  /* each adjacent pair is compared once */\n        while (e < n && less_at(A, e, e - 1)) e++;",
+                                 "if (e < n && !less_at(A, e - 1, e)) {\n        e++;  /* each adjacent pair is compared once */\n        while (e < n && !less_at(A, e - 1, e)) e++;"),
     # midpoint without the half run length
     "midpoint_drops_half_length": ("unsigned __int128 an = 2 * (unsigned __int128)s1 + n1;",
                                    "unsigned __int128 an = 2 * (unsigned __int128)s1;"),
