@@ -375,6 +375,16 @@ def run_batched(args) -> int:
     mp_ms = mp["ms"] / max(mp["launches"], 1)
     ach = (2 * 8 * mp["elems"] / max(mp["launches"], 1)) / (mp_ms / 1e3) / 1e9 if mp_ms > 0 else 0.0
     best_ms = min(eager_ms, graph_ms)
+    # informational: every group of one eager sort timed
+    binding.profile_enable(True)
+    binding.profile_read(reset=True)
+    restore()
+    torch.cuda.synchronize()
+    b.sort()
+    torch.cuda.synchronize()
+    prof_all = binding.profile_read(reset=True)
+    binding.profile_enable(False)
+    groups = {g: round(prof_all[g]["ms"], 3) for g in binding.PROF_GROUPS}
     out = {
         "metric": BATCHED_METRIC,
         "value": round(n / (graph_ms / 1e3), 1),
@@ -394,6 +404,7 @@ def run_batched(args) -> int:
                      "frac": round(ach / (HBM_PEAK_BPS / 1e9), 4), "traffic": None, "kernel": "merge_pass_kernel",
                      "launch_ms": round(mp_ms, 4)},
         "path_roofline": {"algorithmic_bytes": b_alg, "frac": round(b_alg / (best_ms / 1e3) / HBM_PEAK_BPS, 4)},
+        "kernel_groups_ms": groups,
         "gen_s": round(t_gen, 1),
     }
     print(json.dumps(out), flush=True)

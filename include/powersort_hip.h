@@ -71,13 +71,22 @@ typedef enum {
  * peeksort's.  For ps_inspect, powers[j] then holds depth(j) + 1 of node j. */
 #define PS_FLAG_PEEKSORT 1u
 
+/* ps_options.flags: use one scratch copy of the data instead of two.  By
+ * default the scratch holds two copies of keys (and payload), so that every
+ * leaf longer than 4096 elements is merged from where it lies; with this flag
+ * it holds one, and such a leaf is first copied to it when its depth in the
+ * merge tree is odd.  Results are identical; only ps_workspace_bytes and
+ * the data moved change. */
+#define PS_FLAG_COMPACT_SCRATCH 2u
+
 /* Options; a NULL pointer means all defaults.  struct_size must be
  * sizeof(ps_options). */
 typedef struct {
     uint32_t struct_size;
     uint32_t min_run;          /* w of App. B.3/B.4; 0 = default 24 (the paper's
                                   setting); 1 = pure natural runs; at most 64 */
-    uint32_t flags;            /* 0, or PS_FLAG_PEEKSORT; other bits are rejected */
+    uint32_t flags;            /* 0, or PS_FLAG_PEEKSORT and/or PS_FLAG_COMPACT_SCRATCH;
+                                  other bits are rejected */
     uint32_t reserved;
     void *workspace;           /* optional caller-owned device scratch */
     uint64_t workspace_bytes;  /* its size; must be >= ps_workspace_bytes(...) */
@@ -85,7 +94,9 @@ typedef struct {
 
 /* Bytes of device scratch one call needs for n_total elements in
  * num_segments segments (ps_sort: num_segments = 1).  has_payload is 0 or 1.
- * Returns 0 for invalid arguments. */
+ * About 2 n_total (key bytes + 4 if has_payload) plus metadata, or half the
+ * data part with PS_FLAG_COMPACT_SCRATCH in opt->flags.  Returns 0 for
+ * invalid arguments. */
 size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
                           const ps_options *opt);
 

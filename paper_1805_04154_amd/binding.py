@@ -110,14 +110,17 @@ def _check(status: int):
 
 
 METHODS = {"powersort": 0, "peeksort": 1}  # ps_options.flags (PS_FLAG_PEEKSORT = 1)
+FLAG_COMPACT_SCRATCH = 2  # PS_FLAG_COMPACT_SCRATCH
 
 
-def _opts(min_run: int | None, workspace: torch.Tensor | None = None, method: str = "powersort"):
+def _opts(min_run: int | None, workspace: torch.Tensor | None = None, method: str = "powersort",
+          compact_scratch: bool = False):
     if method not in METHODS:
         raise ValueError(f"method must be one of {sorted(METHODS)}")
-    if min_run is None and workspace is None and method == "powersort":
+    if min_run is None and workspace is None and method == "powersort" and not compact_scratch:
         return None
-    o = PsOptions(ctypes.sizeof(PsOptions), int(min_run or 0), METHODS[method], 0, None, 0)
+    flags = METHODS[method] | (FLAG_COMPACT_SCRATCH if compact_scratch else 0)
+    o = PsOptions(ctypes.sizeof(PsOptions), int(min_run or 0), flags, 0, None, 0)
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -146,15 +149,15 @@ def _stream(stream) -> int:
 
 
 def workspace_bytes(n_total: int, num_segments: int, dtype: torch.dtype, has_payload: bool,
-                    min_run: int | None = None, method: str = "powersort") -> int:
+                    min_run: int | None = None, method: str = "powersort", compact_scratch: bool = False) -> int:
     lib = load_library()
     return int(lib.ps_workspace_bytes(n_total, num_segments, KEY_TYPES[dtype], int(has_payload),
-                                      _opts(min_run, None, method)))
+                                      _opts(min_run, None, method, compact_scratch)))
 
 
 def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int | None = None,
          merge_cost: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None,
-         method: str = "powersort"):
+         method: str = "powersort", compact_scratch: bool = False):
     """Stable in-place powersort (or peeksort) of a 1-D device tensor (payload permuted alongside).
 
     merge_cost: optional 1-element int64 device tensor that receives M (as uint64 bits)."""
@@ -163,7 +166,7 @@ def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int |
     if payload is not None and (payload.dtype not in (torch.int32, torch.uint32) or payload.numel() != keys.numel()):
         raise ValueError("payload must be a 32-bit tensor with one entry per key")
     _check(lib.ps_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None, keys.numel(),
-                       _key_type(keys), _opts(min_run, workspace, method),
+                       _key_type(keys), _opts(min_run, workspace, method, compact_scratch),
                        merge_cost.data_ptr() if merge_cost is not None else None, _stream(stream)))
     return keys, payload
 
@@ -171,14 +174,14 @@ def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int |
 def segmented_sort(keys: torch.Tensor, payload: torch.Tensor | None, offsets: torch.Tensor,
                    min_run: int | None = None, merge_costs: torch.Tensor | None = None,
                    status: torch.Tensor | None = None, stream=None, workspace: torch.Tensor | None = None,
-                   method: str = "powersort"):
+                   method: str = "powersort", compact_scratch: bool = False):
     """Sort every segment [offsets[g], offsets[g+1]) independently (offsets: int64 device tensor)."""
     lib = load_library()
     _dev_check(keys, payload, offsets, merge_costs, status)
     nseg = offsets.numel() - 1
     _check(lib.ps_segmented_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None,
                                  offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
-                                 _opts(min_run, workspace, method),
+                                 _opts(min_run, workspace, method, compact_scratch),
                                  merge_costs.data_ptr() if merge_costs is not None else None,
                                  status.data_ptr() if status is not None else None, _stream(stream)))
     return keys, payload

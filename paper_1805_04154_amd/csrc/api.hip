@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void weight_starts_kernel(const uint32_t*
 
 struct Layout {
     size_t total = 0;
-    size_t scratch_keys, scratch_pay, offsets;
+    size_t scratch_keys, scratch_pay, offsets, tile_seg;
     size_t code[4], cnt[4], entry[4], offs[4];
     uint32_t ntab[4];
     int levels;
@@ -175,14 +175,17 @@ static size_t take(size_t& at, size_t bytes) {
     return here;
 }
 
-static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_t w, bool moves, bool peek) {
+static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_t w, bool moves, bool peek,
+                          uint32_t nbuf) {
     Layout L;
     size_t at = 0;
-    L.scratch_keys = moves ? take(at, N * kb) : 0;
-    L.scratch_pay = (moves && hp) ? take(at, N * 4) : 0;
+    // nbuf - 1 scratch arrays of keys (and of payload), back to back
+    L.scratch_keys = moves ? take(at, N * kb * (nbuf - 1)) : 0;
+    L.scratch_pay = (moves && hp) ? take(at, N * 4 * (nbuf - 1)) : 0;
     L.offsets = take(at, (nseg + 1) * 8);
     const uint32_t W1 = w + 1;
     uint32_t nt = (uint32_t)((N + kPartTile - 1) / kPartTile);
+    L.tile_seg = take(at, (size_t)nt * 4);
     L.levels = 0;
     while (true) {
         L.ntab[L.levels] = nt;
@@ -413,21 +416,29 @@ struct Call {
     ps_inspect_out* inspect;    // Mode::Inspect
     Mode mode;
     bool peek = false;          // PS_FLAG_PEEKSORT: Alg. PeekSort's tree instead of node powers
+    uint32_t nbuf = 3;          // data arrays (2 with PS_FLAG_COMPACT_SCRATCH)
 };
 
 static size_t key_bytes(int kt) { return (kt == KT_I64 || kt == KT_U64) ? 8 : 4; }
 
-static ps_status check_common(int kt, const ps_options* opt, uint32_t* w, bool* peek) {
+struct CallOpts {
+    uint32_t w = 24;
+    bool peek = false;
+    uint32_t nbuf = 3;
+};
+
+static ps_status check_common(int kt, const ps_options* opt, CallOpts* o) {
     if (kt < KT_I32 || kt > KT_F32) return fail(PS_ERR_INVALID_ARG, "unknown key type");
-    *w = 24;
-    *peek = false;
+    *o = CallOpts{};
     if (opt) {
         if (opt->struct_size != sizeof(ps_options)) return fail(PS_ERR_INVALID_ARG, "ps_options.struct_size mismatch");
-        if (opt->flags & ~(uint32_t)PS_FLAG_PEEKSORT) return fail(PS_ERR_UNSUPPORTED, "unknown ps_options.flags bits");
-        if (opt->min_run) *w = opt->min_run;
-        *peek = (opt->flags & PS_FLAG_PEEKSORT) != 0;
+        if (opt->flags & ~(uint32_t)(PS_FLAG_PEEKSORT | PS_FLAG_COMPACT_SCRATCH))
+            return fail(PS_ERR_UNSUPPORTED, "unknown ps_options.flags bits");
+        if (opt->min_run) o->w = opt->min_run;
+        o->peek = (opt->flags & PS_FLAG_PEEKSORT) != 0;
+        if (opt->flags & PS_FLAG_COMPACT_SCRATCH) o->nbuf = 2;
     }
-    if (*w > (uint32_t)kMaxMinRun) return fail(PS_ERR_UNSUPPORTED, "min_run above 64 is not supported");
+    if (o->w > (uint32_t)kMaxMinRun) return fail(PS_ERR_UNSUPPORTED, "min_run above 64 is not supported");
     return PS_OK;
 }
 
@@ -444,7 +455,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     const Tuning tune = current_tuning();
     const bool hp = moves && c.payload != nullptr;
     const size_t kb = key_bytes(c.kt);
-    const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves, c.peek);
+    const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves, c.peek, c.nbuf);
     void* ws = nullptr;
     ps_status s = get_workspace(st, L.total, opt, &ws);
     if (s != PS_OK) return s;
@@ -463,6 +474,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     pa.N = N;
     pa.offsets = offsets;
     pa.nseg = nseg;
+    pa.tile_seg = (uint32_t*)at(L.tile_seg);
     pa.w = c.w;
     pa.levels = L.levels;
     for (int l = 0; l < L.levels; ++l) {
@@ -528,6 +540,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ta.lists.node_rec = (NodeRec*)at(L.node_rec);
         ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
         ta.lists.leaf_tile = (uint32_t*)at(L.leaf_tile);
+        ta.lists.nbuf = c.nbuf;
         if (prof_on()) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             ta.prof = g_prof.dev;
@@ -541,8 +554,11 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         MoveArgs ma{};
         ma.keys[0] = c.keys;
         ma.keys[1] = at(L.scratch_keys);
+        ma.keys[2] = c.nbuf == 3 ? (void*)((char*)at(L.scratch_keys) + (size_t)N * kb) : nullptr;
         ma.pay[0] = c.payload;
         ma.pay[1] = hp ? (uint32_t*)at(L.scratch_pay) : nullptr;
+        ma.pay[2] = (hp && c.nbuf == 3) ? (uint32_t*)at(L.scratch_pay) + N : nullptr;
+        ma.leaf_copy = leaf_copy_buf(c.nbuf);
         ma.starts = pa.starts;
         ma.P = ta.P;
         ma.Lf = ta.Lf;
@@ -609,7 +625,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
 // Degenerate inputs (n_total == 0) still report merge costs of zero and a
 // valid status, through the same small kernels.
 static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st) {
-    const Layout L = make_layout(0, c.nseg, key_bytes(c.kt), false, c.w, false, false);
+    const Layout L = make_layout(0, c.nseg, key_bytes(c.kt), false, c.w, false, false, c.nbuf);
     void* ws = nullptr;
     ps_status s = get_workspace(st, L.total, opt, &ws);
     if (s != PS_OK) return s;
@@ -631,12 +647,12 @@ static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st)
 
 static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     g_last_error.clear();
-    uint32_t w;
-    bool peek;
-    ps_status s = check_common(c.kt, opt, &w, &peek);
+    CallOpts o;
+    ps_status s = check_common(c.kt, opt, &o);
     if (s != PS_OK) return s;
-    c.w = w;
-    c.peek = peek;
+    c.w = o.w;
+    c.peek = o.peek;
+    c.nbuf = o.nbuf;
     if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^32");
     if (c.nseg == 0) return fail(PS_ERR_INVALID_ARG, "num_segments must be at least 1");
     if (c.nseg >= kMaxTotal) return fail(PS_ERR_TOO_LARGE, "too many segments");
@@ -750,11 +766,11 @@ extern "C" {
 
 size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
                           const ps_options* opt) {
-    uint32_t w;
-    bool peek;
-    if (check_common((int)key_type, opt, &w, &peek) != PS_OK) return 0;
+    CallOpts o;
+    if (check_common((int)key_type, opt, &o) != PS_OK) return 0;
     if (n_total > kMaxTotal || num_segments == 0 || num_segments >= kMaxTotal) return 0;
-    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, w, true, peek).total;
+    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, o.w, true, o.peek, o.nbuf)
+        .total;
 }
 
 ps_status ps_alphabetic_tree(const uint32_t* d_weights, uint64_t num_leaves, uint8_t* d_powers,

@@ -88,6 +88,25 @@ constexpr uint32_t kMergeTileMin = 2048;
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;
 
+// Where a sorted tree vertex lives.  Array 0 is the caller's, 1 and 2 are
+// scratch.  A merge must not write the array it reads, so a vertex and its
+// children always sit in different arrays.
+//  * Two arrays: the depth parity; a long leaf at odd depth is copied to 1.
+//  * Three arrays: segment roots end in 0, inner nodes alternate 2, 1, 2, ...
+//    by depth, and a leaf longer than a fused subtree stays in place in 0
+//    (reversed there if decreasing) unless its parent is the root, which
+//    writes 0: such a leaf is copied to 2 like the root's other children.
+//    This saves the copy of every long leaf at odd depth for one more
+//    array of scratch.
+__host__ __device__ constexpr uint32_t node_buf(uint32_t depth, uint32_t nbuf) {
+    return nbuf == 3 ? (depth == 0 ? 0u : 1u + (depth & 1u)) : (depth & 1u);
+}
+__host__ __device__ constexpr uint32_t big_leaf_buf(uint32_t depth, uint32_t nbuf) {
+    return nbuf == 3 ? (depth == 1 ? 2u : 0u) : (depth & 1u);
+}
+// The array a long leaf is copied into when it moves.
+__host__ __device__ constexpr uint32_t leaf_copy_buf(uint32_t nbuf) { return nbuf == 3 ? 2u : 1u; }
+
 constexpr int kMaxPower = 32;  // powers are at most floor(lg n) + 1 <= 32 for n < 2^31
 // Merge-pass keys: node powers, or peeksort depth + 1.  A peeksort node at
 // depth d >= 2 covers at most half the elements of its ancestor at depth

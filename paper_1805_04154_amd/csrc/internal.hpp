@@ -22,7 +22,8 @@ struct Mask2 {
 };
 
 struct NodeRec {
-    uint32_t lo, mid, hi, depth;  // a merge of [lo, mid) and [mid, hi); the node's depth
+    uint32_t lo, mid, hi;  // a merge of [lo, mid) and [mid, hi)
+    uint32_t bufs;         // arrays: result (bits 0-1), left child (2-3), right child (4-5)
 };
 struct SplitRec {
     uint32_t node;    // bucket entry of the tile's node
@@ -42,6 +43,7 @@ struct TreeLists {
     NodeRec* node_rec;      // merge record of each bucket entry
     uint32_t* bucket_tile;  // first merge tile of each bucket entry (within its pass)
     uint32_t* leaf_tile;    // first copy tile of each big leaf
+    uint32_t nbuf;          // 2 or 3 data arrays (node_buf / big_leaf_buf)
 };
 
 struct TreeArgs {
@@ -73,6 +75,7 @@ struct PartitionArgs {
     uint32_t N;
     const uint64_t* offsets;
     uint32_t nseg;
+    uint32_t* tile_seg;  // per partition tile: first offsets index >= the tile start (nseg > 1)
     uint32_t w;
     uint8_t* code[4];
     uint32_t* cnt[4];
@@ -86,8 +89,8 @@ struct PartitionArgs {
 };
 
 struct MoveArgs {
-    void* keys[2];
-    uint32_t* pay[2];
+    void* keys[3];      // data arrays: the caller's, then scratch (keys[2] only with three arrays)
+    uint32_t* pay[3];
     const uint32_t* starts;
     const uint8_t* P;
     const uint32_t* Lf;
@@ -106,6 +109,7 @@ struct MoveArgs {
     uint32_t split_cap;        // capacity of split (records)
     uint32_t fuse_max_leaves;  // leaves a fused subtree can hold at this w
     uint32_t merge_tile;       // outputs per merge-path tile
+    uint32_t leaf_copy;        // array that copied long leaves go to (leaf_copy_buf)
 };
 
 // Launch shape chosen by the caller (ps_set_tuning) or the defaults.

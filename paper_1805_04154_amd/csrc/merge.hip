@@ -1,14 +1,15 @@
 // Data movement: forming the leaves and the stable merges of the merge tree.
 //
-// Buffers: buf 0 is the caller's array, buf 1 the library's scratch array.
-// A tree vertex (leaf or node) at depth d keeps its sorted result in
-// buf (d & 1); a node therefore reads both children from buf ((d+1) & 1) and
-// writes buf (d & 1), and the root (depth 0) ends in the caller's array.
+// Arrays: 0 is the caller's, 1 and 2 the library's scratch (2 only when the
+// call has room for it).  Every tree vertex keeps its sorted result in the
+// array node_buf / big_leaf_buf assign to it; a node reads its children from
+// their arrays and writes its own, never one of theirs, and the root
+// (depth 0) ends in the caller's array.
 //
 //  * big_leaf: a leaf longer than the fused-subtree capacity is a natural run
 //    (only shorter leaves are min-run extended); a strictly decreasing one is
-//    reversed (Sec. 2 run convention), and it is copied to buf 1 if its depth
-//    is odd.
+//    reversed (Sec. 2 run convention), in place or while it is copied to
+//    the array its depth assigns.
 //  * fused: every maximal subtree of at most kFuse elements is loaded once
 //    from the caller's array, its leaves are stably sorted in LDS (the
 //    reversal / insertion-sort extension of App. B.3-B.4 has the unique stable
@@ -28,6 +29,17 @@ namespace ps {
 
 constexpr uint32_t kNoneM = 0xFFFFFFFFu;
 
+// Data array b (0, 1, 2) of a MoveArgs pointer triple.
+template <class T>
+__device__ __forceinline__ T* pick3(T* const (&v)[3], uint32_t b) {
+    return b == 0 ? v[0] : (b == 1 ? v[1] : v[2]);
+}
+// The same for a b that is equal across the wave (kept in a scalar register).
+template <class T>
+__device__ __forceinline__ T* pick3u(T* const (&v)[3], uint32_t b) {
+    return pick3(v, (uint32_t)__builtin_amdgcn_readfirstlane(b));
+}
+
 __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__ a, uint32_t n, uint32_t v) {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
@@ -46,7 +58,8 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
     const uint32_t ntiles = a.cnt->ptiles[0];
     const uint32_t nleaf = a.cnt->nbigleaf;
     raw* k0 = (raw*)a.keys[0];
-    raw* k1 = (raw*)a.keys[1];
+    raw* k1 = (raw*)pick3u(a.keys, a.leaf_copy);
+    uint32_t* p1 = pick3u(a.pay, a.leaf_copy);
     if (nleaf == 0) return;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint32_t k = upper_bound_u32(a.leaf_tile, nleaf, t) - 1;
@@ -104,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
                     if (x < x1) {
                         const uint32_t y = rev ? (L - 1 - x) : x;
                         k1[s + y] = kv[j];
-                        if (HP) a.pay[1][s + y] = pv[j];
+                        if (HP) p1[s + y] = pv[j];
                     }
                 }
             }
@@ -266,8 +279,8 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         if (n > (uint32_t)kFuse || n == 0 || !fuse_by_radix(sizeof(U), nleaves)) continue;
         const raw* src = (const raw*)a.keys[0];
-        const uint32_t par = a.unit_par[u];
-        raw* dst = (raw*)a.keys[par];
+        raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
+        uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
         {
             raw kv[kFuseItems];
             uint32_t pv[kFuseItems];
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
             const uint32_t x = tid + i * kFuseThreads;
             if (x < n) {
                 dst[lo + x] = K::unord(ok[x]);
-                if (HP) a.pay[par][lo + x] = op[x];
+                if (HP) pdst[lo + x] = op[x];
             }
         }
         __syncthreads();
@@ -332,8 +345,8 @@ __global__ __launch_bounds__(kFuseThreads) void fused_kernel(MoveArgs a) {
         if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > ML) continue;
         if (fuse_by_radix(sizeof(U), nleaves)) continue;  // fused_radix_kernel's unit
         const raw* src = (const raw*)a.keys[0];
-        const uint32_t par = a.unit_par[u];
-        raw* dst = (raw*)a.keys[par];
+        raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
+        uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
         if (tid == 0) *pmask = 0;
         U kr[kFuseItems];
         uint32_t pr[kFuseItems];
@@ -512,7 +525,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_kernel(MoveArgs a) {
             const uint32_t x = tid + i * kFuseThreads;
             if (x < n) {
                 dst[lo + x] = K::unord(kr[i]);
-                if (HP) a.pay[par][lo + x] = pr[i];
+                if (HP) pdst[lo + x] = pr[i];
             }
         }
         __syncthreads();
@@ -545,9 +558,8 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
     for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
         const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
         const NodeRec R = a.node_rec[bbase + k];
-        const raw* src = (const raw*)a.keys[(R.depth + 1) & 1];
-        const raw* A = src + R.lo;
-        const raw* B = src + R.mid;
+        const raw* A = (const raw*)pick3(a.keys, (R.bufs >> 2) & 3u) + R.lo;
+        const raw* B = (const raw*)pick3(a.keys, (R.bufs >> 4) & 3u) + R.mid;
         const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
         const uint32_t d = (t - a.bucket_tile[bbase + k]) * a.merge_tile;
         uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
@@ -577,11 +589,13 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
         const NodeRec R = a.node_rec[s0.node];
         const uint32_t tt = t - a.bucket_tile[s0.node];
         const uint32_t lo = R.lo, mid = R.mid, hi = R.hi;
-        const uint32_t d = R.depth;
-        const raw* src = (const raw*)a.keys[(d + 1) & 1];
-        raw* dst = (raw*)a.keys[d & 1];
-        const uint32_t* psrc = a.pay[(d + 1) & 1];
-        uint32_t* pdst = a.pay[d & 1];
+        const uint32_t bufs = R.bufs;
+        const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + lo;
+        const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 4) & 3u) + mid;
+        raw* dst = (raw*)pick3u(a.keys, bufs & 3u);
+        const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + lo;
+        const uint32_t* psrcB = pick3u(a.pay, (bufs >> 4) & 3u) + mid;
+        uint32_t* pdst = pick3u(a.pay, bufs & 3u);
         const uint32_t la = mid - lo, tot = hi - lo;
         const uint32_t k0 = tt * TILE, k1 = min(tot, k0 + TILE);
         const uint32_t i0 = s0.corank;
@@ -595,10 +609,14 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
 #pragma unroll
             for (int i = 0; i < kMergeItems; ++i) {
                 const uint32_t x = tid + i * NT;
-                if (x < nt) {
-                    const uint32_t g = (x < na) ? (lo + i0 + x) : (mid + j0 + (x - na));
-                    kv[i] = src[g];
-                    if (HP) pr[i] = psrc[g];
+                // two masked loads with scalar bases (not a per-lane
+                // pointer select, which costs 64-bit address arithmetic)
+                if (x < na) {
+                    kv[i] = srcA[i0 + x];
+                    if (HP) pr[i] = psrcA[i0 + x];
+                } else if (x < nt) {
+                    kv[i] = srcB[j0 + x - na];
+                    if (HP) pr[i] = psrcB[j0 + x - na];
                 }
             }
 #pragma unroll

@@ -60,7 +60,8 @@ struct PartShared {
 // the run's end, beyond the window (exit code w).
 template <int KT>
 __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
-                                const uint64_t* __restrict__ offsets, uint32_t nseg, uint32_t w,
+                                const uint64_t* __restrict__ offsets, uint32_t nseg,
+                                const uint32_t* __restrict__ tile_seg, uint32_t w,
                                 uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
     using K = Key<KT>;
     using U = typename K::ukey;
@@ -83,16 +84,9 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
             if (k < NPW && !(k == 0 && T0 == 0)) sm.u.keys[k] = K::ord(kv[i]);
         }
     }
-    if (tid == 0 && nseg > 1) {
-        // First offset index whose value exceeds T0-1 (segment starts in the window).
-        uint32_t lo = 0, hi = nseg + 1;
-        const uint64_t v = (uint64_t)T0;  // offsets > T0-1  <=>  offsets >= T0
-        while (lo < hi) {
-            uint32_t m = (lo + hi) >> 1;
-            if (offsets[m] < v) lo = m + 1; else hi = m;
-        }
-        sm.gfirst = lo;
-    }
+    // First offset index whose value exceeds T0-1 (segment starts in the
+    // window), found for every tile at once by tile_seg_kernel.
+    if (tid == 0 && nseg > 1) sm.gfirst = tile_seg[T0 / kPartTile];
     __syncthreads();
     for (uint32_t k = tid; k < NPW; k += kThreads) {
         uint8_t t;
@@ -195,13 +189,14 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
 template <int KT>
 __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
-    uint32_t nseg, uint32_t w, uint8_t* __restrict__ tcode, uint32_t* __restrict__ tcnt) {
+    uint32_t nseg, const uint32_t* __restrict__ tile_seg, uint32_t w, uint8_t* __restrict__ tcode,
+    uint32_t* __restrict__ tcnt) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
     const uint32_t W1 = w + 1;
-    if (tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm)) {
+    if (tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm)) {
         // Entering at T0 + c (< T1): one leaf start, then past the window.
         // Entering at the crossing run's end: that end lies past the window.
         for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
@@ -355,7 +350,8 @@ __global__ __launch_bounds__(kThreads) void compose_down_kernel(
 template <int KT>
 __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
-    uint32_t nseg, uint32_t w, const uint8_t* __restrict__ entry, const uint32_t* __restrict__ offs,
+    uint32_t nseg, const uint32_t* __restrict__ tile_seg, uint32_t w, const uint8_t* __restrict__ entry,
+    const uint32_t* __restrict__ offs,
     const uint32_t* __restrict__ tcnt, uint32_t* __restrict__ starts, uint32_t rcap) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
@@ -364,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const uint32_t e = entry[blockIdx.x];
     // No leaf starts in this tile (e.g. it lies inside one long run).
     if (tcnt[(size_t)blockIdx.x * (w + 1) + e] == 0) return;
-    if (tile_successors<KT>(keys, N, offsets, nseg, w, T0, T1, sm)) {
+    if (tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm)) {
         // Inside one long run: the only leaf start is the entry itself.
         const uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
         if (threadIdx.x == 0 && pos < T1) {
@@ -424,13 +420,31 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
 
 // ------------------------------------------------------------- host launch
 
+// For every tile, the first offsets index whose value is >= T0 (a binary
+// search per tile, all tiles at once).
+__global__ __launch_bounds__(kThreads) void tile_seg_kernel(const uint64_t* __restrict__ offsets, uint32_t nseg,
+                                                            uint32_t ntiles, uint32_t* __restrict__ tile_seg) {
+    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
+        const uint64_t v = (uint64_t)t * kPartTile;
+        uint32_t lo = 0, hi = nseg + 1;
+        while (lo < hi) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (offsets[m] < v) lo = m + 1; else hi = m;
+        }
+        tile_seg[t] = lo;
+    }
+}
+
 template <int KT>
 hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
     using raw = typename Key<KT>::raw;
     const uint32_t nT = a.ntab[0];
     const uint32_t W1 = a.w + 1;
+    if (a.nseg > 1)
+        hipLaunchKernelGGL(tile_seg_kernel, dim3(std::min<uint32_t>((nT + kThreads - 1) / kThreads, 4096u)),
+                           dim3(kThreads), 0, st, a.offsets, a.nseg, nT, a.tile_seg);
     hipLaunchKernelGGL(part_tables_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N,
-                       a.offsets, a.nseg, a.w, a.code[0], a.cnt[0]);
+                       a.offsets, a.nseg, a.tile_seg, a.w, a.code[0], a.cnt[0]);
     const size_t lds = (size_t)kScanGroup * W1 * 5;
     for (int l = 0; l + 1 < a.levels; ++l)
         hipLaunchKernelGGL(compose_up_kernel, dim3(a.ntab[l + 1]), dim3(kThreads), lds, st, a.code[l], a.cnt[l],
@@ -442,7 +456,7 @@ hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
                            a.entry[l], a.offs[l], l == 0 ? a.r_dev : nullptr, a.starts, a.N, a.rmax);
     }
     hipLaunchKernelGGL(part_emit_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N, a.offsets,
-                       a.nseg, a.w, a.entry[0], a.offs[0], a.cnt[0], a.starts, a.rmax);
+                       a.nseg, a.tile_seg, a.w, a.entry[0], a.offs[0], a.cnt[0], a.starts, a.rmax);
     return hipGetLastError();
 }
 

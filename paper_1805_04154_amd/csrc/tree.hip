@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         if (unit_node) {
             pr_fused += starts[nrt] - starts[nlf];
             L.unit_rec[slot] = UnitRec{nlf, nrt, starts[nlf], starts[nrt]};
-            L.unit_par[slot] = node_depth[i] & 1;
+            L.unit_par[slot] = node_buf(node_depth[i], L.nbuf);
         }
         // ---- leaf i
         bool unit_leaf = false, big_leaf = false;
@@ -382,8 +382,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             if (len > (uint32_t)kFuse) {
                 big_leaf = true;
                 const bool desc = K::ord(keys[s + 1]) < K::ord(keys[s]);
-                const bool odd = leaf_depth[i] & 1;
-                mode = desc ? (odd ? kLeafRevCopy : kLeafRevInPlace) : (odd ? kLeafCopy : kLeafNoop);
+                const bool moved = big_leaf_buf(leaf_depth[i], L.nbuf) != 0;
+                mode = desc ? (moved ? kLeafRevCopy : kLeafRevInPlace) : (moved ? kLeafCopy : kLeafNoop);
             } else {
                 unit_leaf = (par == kNone) || size_of(par) > (uint32_t)kFuse;
             }
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         if (unit_leaf) {
             pr_fused += starts[i + 1] - starts[i];
             L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
-            L.unit_par[slot] = leaf_depth[i] & 1;
+            L.unit_par[slot] = node_buf(leaf_depth[i], L.nbuf);
         }
         slot = block_append(big_leaf, &cnt->nbigleaf, sh, &base_sh);
         if (big_leaf) {
@@ -499,8 +499,17 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                 else if (mode != kLeafNoop) tiles = (len + kLeafTile - 1) / kLeafTile;
             } else {
                 const uint32_t j = L.bucket[off + k];
-                const uint32_t lo = starts[Lf[j]], hi = starts[Rt[j]];
-                L.node_rec[off + k] = NodeRec{lo, starts[j], hi, node_depth[j]};
+                const uint32_t lf = Lf[j], rt = Rt[j];
+                const uint32_t lo = starts[lf], mid = starts[j], hi = starts[rt];
+                // A child that is one leaf longer than a fused subtree is in
+                // the long-leaf array; any other child is a node or a fused
+                // subtree, in its depth's array.
+                const uint32_t d = node_depth[j];
+                const uint32_t ba = (lf + 1 == j && mid - lo > (uint32_t)kFuse) ? big_leaf_buf(d + 1, L.nbuf)
+                                                                                 : node_buf(d + 1, L.nbuf);
+                const uint32_t bb = (j + 1 == rt && hi - mid > (uint32_t)kFuse) ? big_leaf_buf(d + 1, L.nbuf)
+                                                                                 : node_buf(d + 1, L.nbuf);
+                L.node_rec[off + k] = NodeRec{lo, mid, hi, node_buf(d, L.nbuf) | (ba << 2) | (bb << 4)};
                 tiles = (hi - lo + merge_tile - 1) / merge_tile;
             }
         }

@@ -29,6 +29,10 @@ import torch
 from . import binding
 
 KEY_BYTES = {torch.int32: 4, torch.int64: 8, torch.float32: 4}
+# HBM per admitted key: up to 8 (key) + 4 (payload) in the arena and two
+# copies of both in the sort's scratch.  The sort's metadata (a few bytes
+# per key at the default minimum run) is not counted.
+BYTES_PER_KEY = 36
 
 
 @dataclass
@@ -75,8 +79,7 @@ class SortServer:
         self.min_run = min_run
         self.max_segments = max_segments
         per_slot = self.budget // max(slots, 1)
-        # per key: 8 (key) + 4 (payload) in the arena and as much again in scratch
-        cap = per_slot // 24
+        cap = per_slot // BYTES_PER_KEY
         if max_batch_keys:
             cap = min(cap, int(max_batch_keys))
         if cap < 1:
@@ -170,7 +173,7 @@ class SortServer:
                 rest = []
                 for r in pending:
                     fits_slot = r.keys.dtype == dt and keys + r.n <= s.capacity and len(batch) < self.max_segments
-                    need = 24 * r.n  # arena (<= 12 B/key) + scratch (<= 12 B/key), as in the slot sizing
+                    need = BYTES_PER_KEY * r.n  # as in the slot sizing
                     if fits_slot and self.in_use + held + need <= self.budget:
                         batch.append(r)
                         keys += r.n

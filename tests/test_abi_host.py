@@ -43,8 +43,8 @@ def test_argument_validation_without_launch(lib):
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
     assert lib.ps_sort(fake, None, 10, 0, _opts(binding, min_run=65), None, None) == -5
     assert b"min_run" in lib.ps_last_error()
-    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=2), None, None) == -5  # unknown bit
-    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=3), None, None) == -5
+    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=4), None, None) == -5  # unknown bit
+    assert lib.ps_sort(fake, None, 10, 0, _opts(binding, flags=7), None, None) == -5
     assert lib.ps_sort(fake, None, 10, 0, _opts(binding, size=8), None, None) == -1
     assert lib.ps_sort(fake, None, 10, 7, None, None, None) == -1
     assert lib.ps_sort(None, None, 10, 0, None, None, None) == -1
@@ -74,8 +74,13 @@ def test_workspace_bytes(lib):
     nopay = lib.ps_workspace_bytes(1 << 28, 1, 0, 0, None)
     assert 0 < small < big < wide
     assert nopay < big
-    # scratch for one copy of keys+payload plus metadata well below the data size
-    assert (1 << 28) * 8 <= big < (1 << 28) * 8 * 1.5
+    # scratch for two copies of keys+payload plus metadata well below the data size
+    assert 2 * (1 << 28) * 8 <= big < 2 * (1 << 28) * 8 * 1.25
+    # PS_FLAG_COMPACT_SCRATCH: one copy
+    compact = lib.ps_workspace_bytes(1 << 28, 1, 0, 1, _opts(binding, flags=2))
+    assert big - compact == (1 << 28) * 8
+    peek = lib.ps_workspace_bytes(1 << 28, 1, 0, 1, _opts(binding, flags=1))
+    assert peek - lib.ps_workspace_bytes(1 << 28, 1, 0, 1, _opts(binding, flags=3)) == (1 << 28) * 8
     assert lib.ps_workspace_bytes(10, 0, 0, 1, None) == 0
     assert lib.ps_workspace_bytes(10, 1, 9, 1, None) == 0
     assert lib.ps_workspace_bytes(10, 1, 0, 1, _opts(binding, min_run=99)) == 0

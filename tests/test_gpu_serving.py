@@ -84,7 +84,8 @@ def test_tight_budget_and_plain(trace):
     biggest = max(m.n for m in metas)
     reqs = make_requests(metas, keys, torch)
     # room for one or two requests at a time: admission waits for memory
-    srv = serving.SortServer(hbm_budget_bytes=2 * 24 * biggest + (1 << 20), slots=2)
+    srv = serving.SortServer(hbm_budget_bytes=2 * serving.BYTES_PER_KEY * biggest + (1 << 20),
+                                slots=2)
     done = srv.serve(reqs, realtime=False)
     torch.cuda.synchronize()
     check(done, refs, keys)
@@ -100,6 +101,6 @@ def test_oversized_request_is_rejected(trace):
     metas, keys, refs = trace
     big = max(range(len(metas)), key=lambda i: metas[i].n)
     reqs = make_requests([metas[big]], [keys[big]], torch)
-    srv = serving.SortServer(hbm_budget_bytes=24 * (metas[big].n // 2), slots=1)
+    srv = serving.SortServer(hbm_budget_bytes=serving.BYTES_PER_KEY * (metas[big].n // 2), slots=1)
     with pytest.raises(ValueError):
         srv.serve(reqs, realtime=False)
