@@ -69,7 +69,7 @@ def merge_kernel_digest() -> str:
     src = open(os.path.join(ROOT, "paper_1805_04154_amd", "csrc", "merge.hip")).read()
     a = src.index("template <int KT, int TILE>\nstruct MergeShared")
     a2 = src.index("\n};\n", a)
-    b = src.index("template <int KT, bool HP, int NT>\n__global__ __launch_bounds__(NT) void merge_pass_kernel")
+    b = src.index("template <int KT, bool HP, int NT, int IT>\n__global__ __launch_bounds__(NT) void merge_pass_kernel")
     b2 = src.index("\n}\n", b)
     return hashlib.sha256((src[a:a2] + src[b:b2]).encode()).hexdigest()[:16]
 

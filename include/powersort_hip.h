@@ -174,8 +174,9 @@ ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uin
 
 /* Launch shape of the data-movement kernels (process-wide).  Every value
  * changes only speed, never results: grids are workgroup counts of
- * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048
- * or 4096.  Zero fields keep their current value.  Written by the project's
+ * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048,
+ * 4096 or 8192 (8192 applies to 4-byte keys; 8-byte keys then use 4096).
+ * Zero fields keep their current value.  Written by the project's
  * autotuner for a workload; read back with ps_get_tuning. */
 typedef struct {
     uint32_t struct_size;

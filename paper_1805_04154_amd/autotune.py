@@ -22,7 +22,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "powersort_hip",
 
 def candidates(small: bool = False) -> list[dict]:
     """The search space: merge tile x merge grid x fused grid x split grid."""
-    tiles = (4096, 2048)
+    tiles = (4096, 2048, 8192)
     merge_grids = (1024, 2048, 4096) if not small else (2048,)
     fused_grids = (1024, 2048) if not small else (2048,)
     split_grids = (256, 512, 1024) if not small else (512,)

@@ -455,6 +455,8 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     const Tuning tune = current_tuning();
     const bool hp = moves && c.payload != nullptr;
     const size_t kb = key_bytes(c.kt);
+    // 8192-output tiles need 64 KiB of LDS with 4-byte keys; 8-byte keys use 4096
+    const uint32_t merge_tile = (tune.merge_tile == 8192 && kb == 8) ? 4096u : tune.merge_tile;
     const Layout L = make_layout(c.N, c.nseg, kb, hp, c.w, moves, c.peek, c.nbuf);
     void* ws = nullptr;
     ps_status s = get_workspace(st, L.total, opt, &ws);
@@ -512,7 +514,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     ta.Lf = (uint32_t*)at(L.Lf);
     ta.Rt = (uint32_t*)at(L.Rt);
     ta.nsize = (uint32_t*)at(L.nsize);
-    ta.merge_tile = tune.merge_tile;
+    ta.merge_tile = merge_tile;
     // Peeksort: every internal node sits at depth <= 2 floor(lg n) - 1, so
     // that many + 1 levels build the whole tree (the key bound of kMaxPass).
     const uint32_t peek_levels = std::max<uint32_t>(1, 2 * ilog2_floor(c.N));
@@ -576,7 +578,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.split = (SplitRec*)at(L.split);
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         ma.fuse_max_leaves = fuse_max_leaves(c.w);
-        ma.merge_tile = tune.merge_tile;
+        ma.merge_tile = merge_tile;
         const uint32_t pmax = c.peek ? std::min<uint32_t>(kMaxPass, peek_levels)
                                      : std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
         const uint64_t max_units = c.N / 2 + 1;
@@ -832,8 +834,8 @@ ps_status ps_set_tuning(const ps_tuning* t) {
         return PS_OK;
     }
     if (t->struct_size != sizeof(ps_tuning)) return fail(PS_ERR_INVALID_ARG, "ps_tuning.struct_size mismatch");
-    if (t->merge_tile && t->merge_tile != 2048 && t->merge_tile != 4096)
-        return fail(PS_ERR_INVALID_ARG, "merge_tile must be 2048 or 4096");
+    if (t->merge_tile && t->merge_tile != 2048 && t->merge_tile != 4096 && t->merge_tile != 8192)
+        return fail(PS_ERR_INVALID_ARG, "merge_tile must be 2048, 4096 or 8192");
     const uint32_t grids[4] = {t->grid_big_leaf, t->grid_fused, t->grid_merge, t->grid_split};
     for (uint32_t g : grids)
         if (g > 65536) return fail(PS_ERR_UNSUPPORTED, "grid above 65536");

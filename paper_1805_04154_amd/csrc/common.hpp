@@ -79,9 +79,9 @@ __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nl
 // last leaf of a segment hold >= w elements; natural runs hold >= 2).
 __host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFuse / (w < 2 ? 2 : w) + 1; }
 
-// Global merge passes: merge-path tiles of 8 outputs per thread, 4096
-// outputs (512 threads) by default, 2048 (256 threads) when tuned so.
-constexpr int kMergeItems = 8;
+// Global merge passes: merge-path tiles of 4096 outputs (512 threads x 8)
+// by default; 2048 (256 x 8) or, for 4-byte keys, 8192 (1024 x 8) when
+// tuned so.
 constexpr uint32_t kMergeTileDefault = 4096;
 constexpr uint32_t kMergeTileMin = 2048;
 

@@ -17,6 +17,12 @@
 // visits.  These small tables compose associatively; a hierarchical scan over
 // them yields each tile's true entry, and a second pass over the tile emits
 // the leaf starts.
+//
+// Inside a tile the chain is followed in one of three ways: a tile inside
+// one long run jumps straight past its window; a tile with few run changes
+// and segment starts (at most kWalkMax) walks each chain point by point,
+// finding J from short sorted lists of those positions; any other tile
+// resolves J for every position and follows it by pointer jumping.
 #include "common.hpp"
 #include "block.hpp"
 #include "internal.hpp"
@@ -27,8 +33,23 @@ constexpr int kPairItems = 17;                     // pairs per thread in the wi
 constexpr int kPairCap = kThreads * kPairItems;    // 4352 >= kPartTile + kMaxMinRun + 2
 constexpr uint32_t kFar = 0xFFFFFFFEu;             // a position beyond the tile's window (!= kInf)
 constexpr uint16_t kExitBit = 0x8000u;
+// A chain never takes more steps in a tile than the tile holds run changes
+// and breaks, plus one: every step lands on or passes one of them.
+constexpr uint32_t kWalkMax = 32;
 
 enum : uint8_t { kAsc = 0, kDesc = 1, kBreak = 2, kUnknown = 3 };
+// How tile_successors left the tile.
+enum : int { kTileTable = 0, kTileUniform = 1, kTileWalk = 2 };
+
+// First entry above v of the ascending list a[0..n), or kInf.
+__device__ __forceinline__ uint32_t first_above(const uint16_t* a, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (a[m] <= v) lo = m + 1; else hi = m;
+    }
+    return lo < n ? (uint32_t)a[lo] : kInf;
+}
 
 template <int KT>
 struct PartShared {
@@ -45,21 +66,28 @@ struct PartShared {
         } em;
     } u;
     uint8_t pt[kPairCap];                     // pair type of pair (T0-1+k, T0+k)
+    uint16_t chg[kWalkMax];                   // walk: pairs k > 0 whose type differs from pair k-1
+    uint16_t brk[kWalkMax];                   // walk: pairs k of type kBreak
+    uint32_t nchg, nbrk;
     uint32_t sh[2 * kWaves];
     uint32_t gfirst;
     uint32_t x0;                              // end of the run crossing T0 (kFar / kInf)
     int flag;
 };
 
-// Computes, for every position s of tile [T0, T1), the encoded successor
-// J(s): a tile-local index if J(s) < T1, else kExitBit | exit code.  The
-// result is left in sm.u.pj.nx (aliased by sm.u.em.nx); sm.x0 receives
-// the end of the natural run crossing T0 (kInf if none, kFar if beyond the
-// window).  Returns true, without filling nx, when the whole tile lies
-// inside one natural run that extends past the window: then every J(s) is
-// the run's end, beyond the window (exit code w).
+// Classifies pairs of tile [T0, T1) and its window and sets sm.x0, the end of
+// the natural run crossing T0 (kInf if none, kFar if beyond the window).
+// Returns
+//  * kTileUniform when the whole tile lies inside one natural run that
+//    extends past the window: every J(s) is the run's end, beyond the
+//    window (exit code w);
+//  * kTileWalk when the window holds at most kWalkMax run changes and breaks
+//    together: they are listed in sm.chg / sm.brk, and walk_next gives J;
+//  * kTileTable otherwise, with the encoded successor of every position s in
+//    sm.u.pj.nx (aliased by sm.u.em.nx): a tile-local index if J(s) < T1,
+//    else kExitBit | exit code.
 template <int KT>
-__device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
+__device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
                                 const uint64_t* __restrict__ offsets, uint32_t nseg,
                                 const uint32_t* __restrict__ tile_seg, uint32_t w,
                                 uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
@@ -117,13 +145,14 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
             // or does not exist (a break), or ends at T0 inclusive
             if (tid == 0) sm.x0 = (sm.pt[0] == t1) ? kFar : (sm.pt[0] == kBreak ? kInf : T0 + 1);
             __syncthreads();
-            return true;
+            return kTileUniform;
         }
     }
 
     // Per thread: pairs k = tid*kPairItems + i.
     uint8_t tp[kPairItems];
     uint32_t cpos_min = kInf, bpos_min = kInf;
+    uint32_t counts = 0;  // changes << 16 | breaks
 #pragma unroll
     for (int i = 0; i < kPairItems; ++i) {
         const uint32_t k = tid * kPairItems + i;
@@ -131,6 +160,38 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
         const bool chg = (k < NPW) && k > 0 && tp[i] != sm.pt[k - 1];
         if (chg) cpos_min = min(cpos_min, k);
         if (k < NPW && tp[i] == kBreak) bpos_min = min(bpos_min, k);
+        counts += (chg ? (1u << 16) : 0u) + ((k < NPW && tp[i] == kBreak) ? 1u : 0u);
+    }
+    {
+        uint32_t tot;
+        const uint32_t ex = block_excl_sum(counts, sm.sh, &tot);
+        if ((tot >> 16) + (tot & 0xFFFFu) <= kWalkMax) {
+            // Few changes and breaks: list them in position order.
+            uint32_t oc = ex >> 16, ob = ex & 0xFFFFu;
+#pragma unroll
+            for (int i = 0; i < kPairItems; ++i) {
+                const uint32_t k = tid * kPairItems + i;
+                if (k < NPW && k > 0 && tp[i] != sm.pt[k - 1]) sm.chg[oc++] = (uint16_t)k;
+                if (k < NPW && tp[i] == kBreak) sm.brk[ob++] = (uint16_t)k;
+            }
+            if (tid == 0) {
+                sm.nchg = tot >> 16;
+                sm.nbrk = tot & 0xFFFFu;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                // the run through pair 0 crosses T0 unless that pair is a break
+                const uint8_t t0 = sm.pt[0];
+                if (t0 == kBreak) sm.x0 = kInf;
+                else if (t0 == kUnknown) sm.x0 = kFar;
+                else {
+                    const uint32_t kc = first_above(sm.chg, sm.nchg, 0u);
+                    sm.x0 = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : T0 + kc;
+                }
+            }
+            __syncthreads();
+            return kTileWalk;
+        }
     }
     const uint32_t cex = block_excl_suffix_min(cpos_min, sm.sh);
     const uint32_t bex = block_excl_suffix_min(bpos_min, sm.sh + kWaves);
@@ -180,7 +241,29 @@ __device__ __forceinline__ bool tile_successors(const typename Key<KT>::raw* __r
         sm.u.pj.nx[s - T0] = enc;
     }
     __syncthreads();
-    return false;
+    return kTileTable;
+}
+
+// J(s) for a position s in [T0, T1) of a tile in walk mode: the same rule as
+// the per-position table, with the next change and break from the lists.
+template <int KT>
+__device__ __forceinline__ uint32_t walk_next(const PartShared<KT>& sm, uint32_t T0, uint32_t s, uint32_t w) {
+    const uint32_t k = s - T0 + 1;  // pair (s, s+1)
+    const uint8_t t = sm.pt[k];
+    uint32_t ne;
+    if (t == kBreak) {
+        ne = s + 1;
+    } else if (t == kUnknown) {
+        ne = kFar;
+    } else {
+        const uint32_t kc = first_above(sm.chg, sm.nchg, k);
+        ne = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : T0 + kc;
+    }
+    if (ne == kFar) return kFar;
+    if (ne - s >= w) return ne;
+    const uint32_t kb = first_above(sm.brk, sm.nbrk, k - 1);  // first break >= k
+    const uint32_t seg_end = (kb == kInf) ? kFar : T0 + kb;
+    return min(seg_end, s + w);
 }
 
 // Pass 1: per-tile exit tables.  For candidate c (c < w: position T0+c;
@@ -196,7 +279,8 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
     const uint32_t W1 = w + 1;
-    if (tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm)) {
+    const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);
+    if (mode == kTileUniform) {
         // Entering at T0 + c (< T1): one leaf start, then past the window.
         // Entering at the crossing run's end: that end lies past the window.
         for (uint32_t c = threadIdx.x; c < W1; c += kThreads) {
@@ -207,13 +291,15 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
         return;
     }
 
-    // Pointer jumping to the exits, counting visited positions.  One buffer:
-    // each round reads every position's next state into registers, waits,
-    // then writes them back.
+    // Table mode: pointer jumping to the exits, counting visited positions.
+    // One buffer: each round reads every position's next state into
+    // registers, waits, then writes them back.  Walk mode follows each
+    // candidate's chain below instead.
+    const bool walk = (mode == kTileWalk);
     constexpr int kPJ = kPartTile / kThreads;  // positions per thread
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.pj.ct[i] = 1;
+    for (uint32_t i = threadIdx.x; !walk && i < len; i += kThreads) sm.u.pj.ct[i] = 1;
     __syncthreads();
-    for (int round = 0; round < 16; ++round) {
+    for (int round = 0; !walk && round < 16; ++round) {
         int any = 0;
         uint16_t na[kPJ], nc[kPJ];
 #pragma unroll
@@ -259,6 +345,14 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
         if (pos == kFar || pos >= T1) {
             code = (uint8_t)((pos != kFar && pos - T1 < w) ? (pos - T1) : w);
             cnt = 0;
+        } else if (walk) {
+            uint32_t s = pos;
+            cnt = 0;
+            while (s < T1) {
+                ++cnt;
+                s = walk_next<KT>(sm, T0, s, w);
+            }
+            code = (uint8_t)((s != kFar && s - T1 < w) ? (s - T1) : w);
         } else {
             const uint16_t e = sm.u.pj.nx[pos - T0];
             code = (uint8_t)(e & 0xFF);
@@ -360,7 +454,8 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const uint32_t e = entry[blockIdx.x];
     // No leaf starts in this tile (e.g. it lies inside one long run).
     if (tcnt[(size_t)blockIdx.x * (w + 1) + e] == 0) return;
-    if (tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm)) {
+    const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);
+    if (mode == kTileUniform) {
         // Inside one long run: the only leaf start is the entry itself.
         const uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
         if (threadIdx.x == 0 && pos < T1) {
@@ -371,6 +466,17 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     }
     uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
     if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
+    if (mode == kTileWalk) {
+        // one lane follows the chain; its points are consecutive leaf starts
+        if (threadIdx.x == 0) {
+            uint32_t rank = offs[blockIdx.x];
+            for (uint32_t s = pos; s < T1; s = walk_next<KT>(sm, T0, s, w)) {
+                if (rank < rcap) starts[rank] = s;
+                ++rank;
+            }
+        }
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < len; i += kThreads) sm.u.em.mk[i] = (i == pos - T0);
     __syncthreads();
     constexpr int kPJ = kPartTile / kThreads;  // positions per thread

@@ -97,6 +97,10 @@ def test_tuning_roundtrip_on_host():
     with pytest.raises(binding.PowersortError):
         binding.set_tuning({"merge_tile": 1000})
     with pytest.raises(binding.PowersortError):
+        binding.set_tuning({"merge_tile": 16384})
+    binding.set_tuning({"merge_tile": 8192})
+    assert binding.get_tuning()["merge_tile"] == 8192
+    with pytest.raises(binding.PowersortError):
         binding.set_tuning({"grid_split": 1 << 20})
     binding.set_tuning(None)
     assert binding.get_tuning() == d

@@ -71,7 +71,8 @@ def test_tunings_do_not_change_results(setup):
     batched, binding, wl, (rk, rp, rc) = setup
     try:
         for t in ({"merge_tile": 2048}, {"merge_tile": 4096, "grid_merge": 64, "grid_split": 3},
-                  {"merge_tile": 2048, "grid_fused": 5, "grid_big_leaf": 7, "grid_merge": 4096}):
+                  {"merge_tile": 2048, "grid_fused": 5, "grid_big_leaf": 7, "grid_merge": 4096},
+                  {"merge_tile": 8192}, {"merge_tile": 8192, "grid_merge": 37, "grid_split": 5}):
             binding.set_tuning(t)
             b = run_eager(batched, wl)
             assert np.array_equal(to_host(b.keys, np.int32), rk), t

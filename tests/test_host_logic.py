@@ -61,7 +61,7 @@ def test_autotuner_search_space():
         assert len(set(keys)) == len(keys)
         for c in cands:
             assert set(c) <= set(TUNING_FIELDS)
-            assert c["merge_tile"] in (2048, 4096)
+            assert c["merge_tile"] in (2048, 4096, 8192)
             assert all(1 <= c[k] <= 65536 for k in c if k.startswith("grid_"))
     import torch
     assert autotune.signature(3 << 20, 4096, torch.int32, None) == autotune.signature(2 << 20, 5000, torch.int32, 24)
