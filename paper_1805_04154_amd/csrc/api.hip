@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void weight_starts_kernel(const uint32_t*
 
 struct Layout {
     size_t total = 0;
-    size_t scratch_keys, scratch_pay, offsets, tile_seg;
+    size_t scratch_keys, scratch_pay, offsets, tile_seg, tile_rec;
     size_t code[4], cnt[4], entry[4], offs[4];
     uint32_t ntab[4];
     int levels;
@@ -186,6 +186,7 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
     const uint32_t W1 = w + 1;
     uint32_t nt = (uint32_t)((N + kPartTile - 1) / kPartTile);
     L.tile_seg = take(at, (size_t)nt * 4);
+    L.tile_rec = take(at, (size_t)nt * sizeof(TileRec));
     L.levels = 0;
     while (true) {
         L.ntab[L.levels] = nt;
@@ -477,6 +478,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     pa.offsets = offsets;
     pa.nseg = nseg;
     pa.tile_seg = (uint32_t*)at(L.tile_seg);
+    pa.tile_rec = (TileRec*)at(L.tile_rec);
     pa.w = c.w;
     pa.levels = L.levels;
     for (int l = 0; l < L.levels; ++l) {

@@ -70,12 +70,28 @@ struct TreeArgs {
     unsigned long long* prof;  // profiling element counters (nullable), indexed by PS_PROF_* group
 };
 
+// Partition: how a tile follows its chain and, for a tile with few run
+// changes and breaks, the lists that define its successor function.  The
+// tables pass writes one per tile; the emit pass reads it instead of the
+// tile's keys unless the tile needs the per-position table.
+constexpr uint32_t kWalkMax = 32;
+struct TileRec {
+    uint32_t x0;                // end of the natural run crossing the tile start
+    uint8_t mode;               // kTileTable / kTileUniform / kTileWalk
+    uint8_t t0;                 // type of the window's first pair
+    uint8_t nchg, nbrk;         // list lengths (walk tiles)
+    uint16_t chg[kWalkMax];     // pairs whose type differs from the previous pair's
+    uint16_t brk[kWalkMax];     // break pairs
+    uint8_t ctype[kWalkMax];    // type of pair chg[i]
+};
+
 struct PartitionArgs {
     const void* keys;
     uint32_t N;
     const uint64_t* offsets;
     uint32_t nseg;
     uint32_t* tile_seg;  // per partition tile: first offsets index >= the tile start (nseg > 1)
+    TileRec* tile_rec;   // per partition tile
     uint32_t w;
     uint8_t* code[4];
     uint32_t* cnt[4];

@@ -33,9 +33,9 @@ constexpr int kPairItems = 17;                     // pairs per thread in the wi
 constexpr int kPairCap = kThreads * kPairItems;    // 4352 >= kPartTile + kMaxMinRun + 2
 constexpr uint32_t kFar = 0xFFFFFFFEu;             // a position beyond the tile's window (!= kInf)
 constexpr uint16_t kExitBit = 0x8000u;
-// A chain never takes more steps in a tile than the tile holds run changes
-// and breaks, plus one: every step lands on or passes one of them.
-constexpr uint32_t kWalkMax = 32;
+// kWalkMax (internal.hpp): a chain never takes more steps in a tile than the
+// tile holds run changes and breaks, plus one: every step lands on or passes
+// one of them.
 
 enum : uint8_t { kAsc = 0, kDesc = 1, kBreak = 2, kUnknown = 3 };
 // How tile_successors left the tile.
@@ -68,6 +68,7 @@ struct PartShared {
     uint8_t pt[kPairCap];                     // pair type of pair (T0-1+k, T0+k)
     uint16_t chg[kWalkMax];                   // walk: pairs k > 0 whose type differs from pair k-1
     uint16_t brk[kWalkMax];                   // walk: pairs k of type kBreak
+    uint8_t ctype[kWalkMax];                  // walk (emit): type of pair chg[i]
     uint32_t nchg, nbrk;
     uint32_t sh[2 * kWaves];
     uint32_t gfirst;
@@ -273,13 +274,32 @@ template <int KT>
 __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
     uint32_t nseg, const uint32_t* __restrict__ tile_seg, uint32_t w, uint8_t* __restrict__ tcode,
-    uint32_t* __restrict__ tcnt) {
+    uint32_t* __restrict__ tcnt, TileRec* __restrict__ tile_rec) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
     const uint32_t W1 = w + 1;
     const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);
+    {
+        // the record the emit pass follows instead of reloading the keys
+        TileRec* R = tile_rec + blockIdx.x;
+        const uint32_t tid = threadIdx.x;
+        if (tid == 0) {
+            R->x0 = sm.x0;
+            R->mode = (uint8_t)mode;
+            R->t0 = sm.pt[0];
+            R->nchg = (uint8_t)(mode == kTileWalk ? sm.nchg : 0u);
+            R->nbrk = (uint8_t)(mode == kTileWalk ? sm.nbrk : 0u);
+        }
+        if (mode == kTileWalk) {
+            if (tid < sm.nchg) {
+                R->chg[tid] = sm.chg[tid];
+                R->ctype[tid] = sm.pt[sm.chg[tid]];
+            }
+            if (tid < sm.nbrk) R->brk[tid] = sm.brk[tid];
+        }
+    }
     if (mode == kTileUniform) {
         // Entering at T0 + c (< T1): one leaf start, then past the window.
         // Entering at the crossing run's end: that end lies past the window.
@@ -445,30 +465,64 @@ template <int KT>
 __global__ __launch_bounds__(kThreads) void part_emit_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
     uint32_t nseg, const uint32_t* __restrict__ tile_seg, uint32_t w, const uint8_t* __restrict__ entry,
-    const uint32_t* __restrict__ offs,
-    const uint32_t* __restrict__ tcnt, uint32_t* __restrict__ starts, uint32_t rcap) {
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tcnt, const TileRec* __restrict__ tile_rec,
+    uint32_t* __restrict__ starts, uint32_t rcap) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
     const uint32_t e = entry[blockIdx.x];
+    const uint32_t tid = threadIdx.x;
     // No leaf starts in this tile (e.g. it lies inside one long run).
     if (tcnt[(size_t)blockIdx.x * (w + 1) + e] == 0) return;
-    const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);
-    if (mode == kTileUniform) {
+    const TileRec* R = tile_rec + blockIdx.x;
+    const int rmode = R->mode;
+    if (rmode == kTileUniform) {
         // Inside one long run: the only leaf start is the entry itself.
-        const uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
-        if (threadIdx.x == 0 && pos < T1) {
+        const uint32_t pos = (e < w) ? (T0 + e) : R->x0;
+        if (tid == 0 && pos < T1) {
             const uint32_t rank = offs[blockIdx.x];
             if (rank < rcap) starts[rank] = pos;
         }
         return;
     }
+    int mode = kTileWalk;
+    if (rmode == kTileWalk) {
+        // Rebuild the window's pair types and lists from the record: a pair's
+        // type is that of the last change at or before it (or of pair 0).
+        const uint32_t nchg = R->nchg, nbrk = R->nbrk;
+        if (tid < nchg) {
+            sm.chg[tid] = R->chg[tid];
+            sm.ctype[tid] = R->ctype[tid];
+        }
+        if (tid < nbrk) sm.brk[tid] = R->brk[tid];
+        if (tid == 0) {
+            sm.nchg = nchg;
+            sm.nbrk = nbrk;
+            sm.x0 = R->x0;
+        }
+        __syncthreads();
+        const uint32_t WE = (uint32_t)min<uint64_t>((uint64_t)N, (uint64_t)T1 + w + 1);
+        const uint32_t NPW = WE - T0 + 1;
+        const uint32_t k0 = tid * kPairItems;
+        uint32_t idx = 0;
+        while (idx < nchg && sm.chg[idx] <= k0) ++idx;
+        const uint8_t t0 = R->t0;
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i) {
+            const uint32_t k = k0 + i;
+            if (idx < nchg && sm.chg[idx] == k) ++idx;
+            if (k < NPW) sm.pt[k] = idx ? sm.ctype[idx - 1] : t0;
+        }
+        __syncthreads();
+    } else {
+        mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);  // kTileTable again
+    }
     uint32_t pos = (e < w) ? (T0 + e) : sm.x0;
     if (pos == kFar || pos == kInf || pos >= T1) return;  // the chain skips this tile
     if (mode == kTileWalk) {
         // one lane follows the chain; its points are consecutive leaf starts
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             uint32_t rank = offs[blockIdx.x];
             for (uint32_t s = pos; s < T1; s = walk_next<KT>(sm, T0, s, w)) {
                 if (rank < rcap) starts[rank] = s;
@@ -550,7 +604,7 @@ hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(tile_seg_kernel, dim3(std::min<uint32_t>((nT + kThreads - 1) / kThreads, 4096u)),
                            dim3(kThreads), 0, st, a.offsets, a.nseg, nT, a.tile_seg);
     hipLaunchKernelGGL(part_tables_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N,
-                       a.offsets, a.nseg, a.tile_seg, a.w, a.code[0], a.cnt[0]);
+                       a.offsets, a.nseg, a.tile_seg, a.w, a.code[0], a.cnt[0], a.tile_rec);
     const size_t lds = (size_t)kScanGroup * W1 * 5;
     for (int l = 0; l + 1 < a.levels; ++l)
         hipLaunchKernelGGL(compose_up_kernel, dim3(a.ntab[l + 1]), dim3(kThreads), lds, st, a.code[l], a.cnt[l],
@@ -562,7 +616,7 @@ hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
                            a.entry[l], a.offs[l], l == 0 ? a.r_dev : nullptr, a.starts, a.N, a.rmax);
     }
     hipLaunchKernelGGL(part_emit_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N, a.offsets,
-                       a.nseg, a.tile_seg, a.w, a.entry[0], a.offs[0], a.cnt[0], a.starts, a.rmax);
+                       a.nseg, a.tile_seg, a.w, a.entry[0], a.offs[0], a.cnt[0], a.tile_rec, a.starts, a.rmax);
     return hipGetLastError();
 }
 

@@ -439,16 +439,23 @@ __device__ __forceinline__ uint32_t wave_count_by_key(bool active, uint32_t key,
     return slot;
 }
 
-// Big nodes per power.
+// Big nodes per power: counted per block in LDS, then one atomic per
+// power per block (a few dozen global counters take every update).
 __global__ __launch_bounds__(kThreads) void bucket_count_kernel(const uint8_t* __restrict__ P,
                                                                  Counters* __restrict__ cnt, TreeLists L) {
+    __shared__ uint32_t h[kMaxPass + 1];
     const uint32_t nbig = cnt->nbig;
+    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads) h[i] = 0;
+    __syncthreads();
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nbig;
         const uint32_t p = valid ? P[L.biglist[k]] : 0;
-        wave_count_by_key(valid, p, cnt->pcount);
+        wave_count_by_key(valid, p, h);
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads)
+        if (h[i]) atomicAdd(&cnt->pcount[i], h[i]);
 }
 
 __global__ void bucket_base_kernel(Counters* cnt) {
@@ -462,16 +469,30 @@ __global__ void bucket_base_kernel(Counters* cnt) {
     }
 }
 
+// Each block counts its nodes per power in LDS, reserves that many slots
+// of every bucket with one atomic per power, then hands them out in LDS.
 __global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint8_t* __restrict__ P,
                                                                    Counters* __restrict__ cnt, TreeLists L) {
+    __shared__ uint32_t h[kMaxPass + 1];
     const uint32_t nbig = cnt->nbig;
+    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads) h[i] = 0;
+    __syncthreads();
+    for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
+        const uint32_t k = k0 + threadIdx.x;
+        const bool valid = k < nbig;
+        wave_count_by_key(valid, valid ? P[L.biglist[k]] : 0u, h);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads)
+        if (h[i]) h[i] = cnt->pbase[i] + atomicAdd(&cnt->pfill[i], h[i]);
+    __syncthreads();
+    // h[p] is now the block's next free slot of bucket p
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nbig;
         const uint32_t j = valid ? L.biglist[k] : 0;
-        const uint32_t p = valid ? P[j] : 0;
-        const uint32_t slot = wave_count_by_key(valid, p, cnt->pfill);
-        if (valid) L.bucket[cnt->pbase[p] + slot] = j;
+        const uint32_t slot = wave_count_by_key(valid, valid ? P[j] : 0u, h);
+        if (valid) L.bucket[slot] = j;
     }
 }
 
@@ -483,20 +504,26 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                                                               Counters* __restrict__ cnt, TreeLists L,
                                                               uint32_t merge_tile) {
     __shared__ uint32_t sh[kWaves];
+    constexpr int kIt = 8;  // entries per thread per step, in position order
     const uint32_t p = blockIdx.x;
     const uint32_t n = (p == 0) ? cnt->nbigleaf : cnt->pcount[p];
     const uint32_t off = (p == 0) ? 0 : cnt->pbase[p];
     uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < n; c0 += kThreads) {
-        const uint32_t k = c0 + threadIdx.x;
-        uint32_t tiles = 0;
-        if (k < n) {
+    for (uint32_t c0 = 0; c0 < n; c0 += kThreads * kIt) {
+        // all of a step's loads are independent, so they overlap
+        uint32_t tiles[kIt];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const uint32_t k = c0 + threadIdx.x * kIt + it;
+            tiles[it] = 0;
+            if (k >= n) continue;
             if (p == 0) {
                 const uint32_t i = L.bigleaf[k];
                 const uint32_t len = starts[i + 1] - starts[i];
                 const uint8_t mode = L.bigleaf_mode[k];
-                if (mode == kLeafRevInPlace) tiles = (len / 2 + kLeafTile - 1) / kLeafTile;
-                else if (mode != kLeafNoop) tiles = (len + kLeafTile - 1) / kLeafTile;
+                if (mode == kLeafRevInPlace) tiles[it] = (len / 2 + kLeafTile - 1) / kLeafTile;
+                else if (mode != kLeafNoop) tiles[it] = (len + kLeafTile - 1) / kLeafTile;
             } else {
                 const uint32_t j = L.bucket[off + k];
                 const uint32_t lf = Lf[j], rt = Rt[j];
@@ -510,14 +537,20 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                 const uint32_t bb = (j + 1 == rt && hi - mid > (uint32_t)kFuse) ? big_leaf_buf(d + 1, L.nbuf)
                                                                                  : node_buf(d + 1, L.nbuf);
                 L.node_rec[off + k] = NodeRec{lo, mid, hi, node_buf(d, L.nbuf) | (ba << 2) | (bb << 4)};
-                tiles = (hi - lo + merge_tile - 1) / merge_tile;
+                tiles[it] = (hi - lo + merge_tile - 1) / merge_tile;
             }
+            sum += tiles[it];
         }
         uint32_t total;
-        const uint32_t ex = block_excl_sum(tiles, sh, &total);
-        if (k < n) {
-            if (p == 0) L.leaf_tile[k] = carry + ex;
-            else L.bucket_tile[off + k] = carry + ex;
+        uint32_t run = carry + block_excl_sum(sum, sh, &total);
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const uint32_t k = c0 + threadIdx.x * kIt + it;
+            if (k < n) {
+                if (p == 0) L.leaf_tile[k] = run;
+                else L.bucket_tile[off + k] = run;
+            }
+            run += tiles[it];
         }
         carry += total;
     }
