@@ -321,6 +321,51 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
 // LDS also fits) at the price of a 32-byte spill: the kernel waits on
 // latency, and the third block hides more of it (4096 random-runs segments
 // of 2^10..2^22 keys: 20.6 -> 16.9 ms).
+// A fused unit that is a single natural run (longer than any min-run
+// extension): copied to its array, reversed if strictly decreasing, without
+// LDS.  Every element is loaded before any is stored, since a run that is a
+// whole segment is written in place.
+template <int KT, bool HP>
+__global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
+    using K = Key<KT>;
+    using raw = typename K::raw;
+    const uint32_t nunits = a.cnt->nunits;
+    const uint32_t tid = threadIdx.x;
+    const raw* src = (const raw*)a.keys[0];
+    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+        const UnitRec ur = a.unit_rec[u];
+        const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
+        if (ur.ub - ur.ua != 1 || n <= (uint32_t)kMaxMinRun || n > (uint32_t)kFuse) continue;
+        raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
+        uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
+        const bool desc = K::ord(src[lo + 1]) < K::ord(src[lo]);
+        const bool in_place = (const void*)dst == (const void*)src;
+        raw kv[kFuseItems];
+        uint32_t pv[kFuseItems];
+#pragma unroll
+        for (int i = 0; i < kFuseItems; ++i) {
+            const uint32_t x = tid + i * kFuseThreads;
+            if (x < n) {
+                kv[i] = src[lo + x];
+                if (HP) pv[i] = a.pay[0][lo + x];
+            }
+        }
+        __syncthreads();
+        if (desc || !in_place) {
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = tid + i * kFuseThreads;
+                if (x < n) {
+                    const uint32_t y = desc ? n - 1 - x : x;
+                    dst[lo + y] = kv[i];
+                    if (HP) pdst[lo + y] = pv[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int KT, bool HP>
 __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6))) void fused_kernel(MoveArgs a) {
     using K = Key<KT>;
@@ -348,6 +393,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         const uint32_t nleaves = ub - ua, nnodes = nleaves - 1;
         if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > ML) continue;
         if (fuse_by_radix(sizeof(U), nleaves)) continue;  // fused_radix_kernel's unit
+        if (nleaves == 1 && n > (uint32_t)kMaxMinRun) continue;  // unit_copy_kernel's unit
         const raw* src = (const raw*)a.keys[0];
         raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
         uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
@@ -389,17 +435,22 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         // Leaf formation: each leaf is stably sorted in place.
         uint16_t np[kFuseItems];
         const uint32_t x0 = tid * kFuseItems;
+        // leaf of x0 (lst[l] <= x0 < lst[l+1]); the thread's later elements
+        // advance from it
+        uint32_t l = 0;
+        {
+            uint32_t h = nleaves;
+            while (l + 1 < h) {
+                const uint32_t mm = (l + h) >> 1;
+                if (lst[mm] <= x0) l = mm; else h = mm;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < kFuseItems; ++i) {
             const uint32_t x = x0 + i;
             np[i] = 0;
             if (x < n) {
-                // leaf l: lst[l] <= x < lst[l+1]
-                uint32_t l = 0, h = nleaves;
-                while (l + 1 < h) {
-                    const uint32_t mm = (l + h) >> 1;
-                    if (lst[mm] <= x) l = mm; else h = mm;
-                }
+                while (lst[l + 1] <= x) ++l;
                 const uint32_t ls = lst[l], le = lst[l + 1];
                 const U key = sk[x];
                 uint32_t dpos;
@@ -706,6 +757,7 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         }
         launch(fused_kernel<KT, HP>, grid, kFuseThreads, lds, st, ev0, ev1, a);
     }
+    else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
         if (kb != 4) return;  // only 4-byte keys take the radix path
