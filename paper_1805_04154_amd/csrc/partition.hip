@@ -55,7 +55,6 @@ template <int KT>
 struct PartShared {
     using U = typename Key<KT>::ukey;
     union {
-        U keys[kPairCap + 1];                 // window keys, position T0-1+k at index k
         struct {
             uint16_t nx[kPartTile];           // successor (or exit) per tile position
             uint16_t ct[kPartTile];           // leaf starts up to the exit
@@ -65,6 +64,7 @@ struct PartShared {
             uint8_t mk[kPartTile];            // chain-point marks
         } em;
     } u;
+    U edge[kWaves][kPairItems + 1];           // each wave's lane-0 keys (the previous wave's right neighbours)
     uint8_t pt[kPairCap];                     // pair type of pair (T0-1+k, T0+k)
     uint16_t chg[kWalkMax];                   // walk: pairs k > 0 whose type differs from pair k-1
     uint16_t brk[kWalkMax];                   // walk: pairs k of type kBreak
@@ -101,30 +101,61 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
 
     {
         // All of this thread's window loads are issued before the first use.
+        // Lane L holds window index tid + i * kThreads; its right neighbour
+        // is lane L+1's, or, for a wave's last lane, the next wave's lane 0
+        // (passed through LDS).  The pair types are computed in registers:
+        // the keys themselves never go to LDS.
+        const int lane = tid & 63, wv = tid >> 6;
         typename K::raw kv[kPairItems];
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i) {
             const uint32_t k = tid + i * kThreads;
             if (k < NPW && !(k == 0 && T0 == 0)) kv[i] = keys[T0 - 1 + k];
         }
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < kPairItems; ++i) sm.edge[wv][i] = K::ord(kv[i]);
+        }
+        if (tid == 0 && nseg > 1) sm.gfirst = tile_seg[T0 / kPartTile];  // first offset >= T0
+        __syncthreads();
+        bool any_asc = false, any_desc = false;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i) {
             const uint32_t k = tid + i * kThreads;
-            if (k < NPW && !(k == 0 && T0 == 0)) sm.u.keys[k] = K::ord(kv[i]);
+            const U u = K::ord(kv[i]);
+            U v = __shfl_down(u, 1);
+            if (lane == 63) v = (wv + 1 < kWaves) ? sm.edge[wv + 1][i] : sm.edge[0][i + 1];
+            if (k < NPW) {
+                uint8_t t;
+                if (k == 0 && T0 == 0) {
+                    t = kBreak;                                  // nothing left of position 0
+                } else if (k + 1 < NPW) {
+                    t = (v < u) ? kDesc : kAsc;
+                    if (k >= 1) {
+                        any_desc |= (t == kDesc);
+                        any_asc |= (t == kAsc);
+                    }
+                } else {
+                    t = (WE == N) ? kBreak : kUnknown;           // pair (WE-1, WE)
+                }
+                sm.pt[k] = t;
+            }
+        }
+        // Inside one long run?  Every pair 1..NPW-2 has one direction, the
+        // window ends before N, and no segment starts inside it.
+        const bool seg_inside = nseg > 1 && sm.gfirst <= nseg && offsets[sm.gfirst] <= (uint64_t)WE;
+        const bool asc = __syncthreads_or(any_asc), desc = __syncthreads_or(any_desc);
+        if (asc != desc && WE < N && !seg_inside) {
+            if (tid == 0) {
+                // the run through pair (T0-1, T0) either continues (same
+                // direction), or does not exist (a break), or ends at T0
+                const uint8_t t0 = sm.pt[0], t1 = desc ? (uint8_t)kDesc : (uint8_t)kAsc;
+                sm.x0 = (t0 == t1) ? kFar : (t0 == kBreak ? kInf : T0 + 1);
+            }
+            __syncthreads();
+            return kTileUniform;
         }
     }
-    // First offset index whose value exceeds T0-1 (segment starts in the
-    // window), found for every tile at once by tile_seg_kernel.
-    if (tid == 0 && nseg > 1) sm.gfirst = tile_seg[T0 / kPartTile];
-    __syncthreads();
-    for (uint32_t k = tid; k < NPW; k += kThreads) {
-        uint8_t t;
-        if (k == 0 && T0 == 0) t = kBreak;               // nothing left of position 0
-        else if (k + 1 < NPW) t = (sm.u.keys[k + 1] < sm.u.keys[k]) ? kDesc : kAsc;
-        else t = (WE == N) ? kBreak : kUnknown;         // pair (WE-1, WE)
-        sm.pt[k] = t;
-    }
-    __syncthreads();
     // A segment start o in (T0-1, WE] breaks pair o-1: runs never cross it.
     // (With one segment the only starts are 0 and N, handled above.)
     for (uint32_t g = sm.gfirst + tid; nseg > 1 && g <= nseg; g += kThreads) {
@@ -133,22 +164,6 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         if (o >= 1 && o >= (uint64_t)T0) sm.pt[(uint32_t)(o - T0)] = kBreak;
     }
     __syncthreads();
-
-    // Fast path: every pair from T0 to the end of the window has the same
-    // direction and the window ends inside the run, so every position of the
-    // tile jumps past the window (to the end of this run).
-    {
-        const uint8_t t1 = sm.pt[1];
-        int uniform = (t1 == kAsc || t1 == kDesc) && sm.pt[NPW - 1] == kUnknown;
-        for (uint32_t k = 1 + tid; uniform && k + 1 < NPW; k += kThreads) uniform = (sm.pt[k] == t1);
-        if (__syncthreads_and(uniform)) {
-            // the run through pair (T0-1, T0) either continues (same direction),
-            // or does not exist (a break), or ends at T0 inclusive
-            if (tid == 0) sm.x0 = (sm.pt[0] == t1) ? kFar : (sm.pt[0] == kBreak ? kInf : T0 + 1);
-            __syncthreads();
-            return kTileUniform;
-        }
-    }
 
     // Per thread: pairs k = tid*kPairItems + i.
     uint8_t tp[kPairItems];
@@ -208,7 +223,6 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         if (k < NPW && tp[i] == kBreak) runb = k;
         nextb[i] = runb;
     }
-    __syncthreads();  // the key window is dead from here on (aliased by nx)
 
 #pragma unroll
     for (int i = 0; i < kPairItems; ++i) {
