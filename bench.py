@@ -74,10 +74,11 @@ def merge_kernel_digest() -> str:
     return hashlib.sha256((src[a:a2] + src[b:b2]).encode()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, launches_per_sort: int):
     """HBM bytes per merge-pass launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy), if
-    it was taken on this workload and on the current kernel source; else None."""
+    it was taken on this workload, on the current kernel source and with the
+    same number of merge launches per sort; else None."""
     try:
         text = open(COUNTERS_MD).read()
     except OSError:
@@ -88,6 +89,8 @@ def measured_traffic(workload: str):
             k, v = line[2:].split(": ", 1)
             fields[k.strip()] = v.strip().strip("`")
     if fields.get("workload") != workload or fields.get("kernel_source_digest") != merge_kernel_digest():
+        return None
+    if fields.get("merge_launches_per_sort") != str(launches_per_sort):
         return None
     try:
         return int(fields["hbm_bytes_per_launch"])
@@ -244,7 +247,9 @@ def main() -> int:
     mp_bytes_per_launch = mp_bytes / max(mp["launches"], 1)
     achieved_gbs = (mp_bytes_per_launch / (mp_launch_ms / 1e3)) / 1e9 if mp_launch_ms > 0 else 0.0
     peak_gbs = HBM_PEAK_BPS / 1e9
-    traffic = measured_traffic(wl.name) if (args.min_run == 24 and args.method == "powersort") else None
+    launches_per_sort = mp["launches"] // max(args.steps, 1)
+    traffic = (measured_traffic(wl.name, launches_per_sort) if (args.min_run == 24 and args.method == "powersort")
+               else None)
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": peak_gbs, "unit": "GB/s",
                 "frac": round(achieved_gbs / peak_gbs, 4), "traffic": traffic,
                 "kernel": "merge_pass_kernel", "launch_ms": round(mp_launch_ms, 4),

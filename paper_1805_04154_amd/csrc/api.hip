@@ -581,8 +581,14 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         ma.fuse_max_leaves = fuse_max_leaves(c.w);
         ma.merge_tile = merge_tile;
+        // Powers: by the definition of a node power, P_j <= ceil(lg(2n / (L_{j-1}
+        // + L_j))), and two adjacent leaves of a segment hold at least w + 1
+        // elements (only a segment's last leaf may be shorter than w), so no
+        // node of a segment of at most N keys has a power above pbound.
+        uint32_t pbound = 1;
+        while (((uint64_t)1 << pbound) * (c.w + 1) < 2 * c.N) ++pbound;
         const uint32_t pmax = c.peek ? std::min<uint32_t>(kMaxPass, peek_levels)
-                                     : std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1);
+                                     : std::min<uint32_t>(std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1), pbound);
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
         auto stage = [&](int group, int s, uint32_t p, uint32_t grid) {

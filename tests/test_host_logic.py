@@ -66,3 +66,30 @@ def test_autotuner_search_space():
     import torch
     assert autotune.signature(3 << 20, 4096, torch.int32, None) == autotune.signature(2 << 20, 5000, torch.int32, 24)
     assert autotune.signature(1 << 20, 1, torch.int32, None) != autotune.signature(1 << 21, 1, torch.int32, None)
+
+
+def pass_bound(n: int, w: int) -> int:
+    """Largest merge pass the library launches for n keys at minimum run w:
+    the smallest l >= 1 with 2^l (w + 1) >= 2n, capped at floor(lg n) + 1."""
+    b = 1
+    while (1 << b) * (w + 1) < 2 * n:
+        b += 1
+    return min(b, max(n, 1).bit_length())
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 7, 24, 64])
+def test_every_node_power_is_within_the_pass_bound(w):
+    # the library runs merge passes pmax..1 only; a node above the bound
+    # would never merge, so the oracle's powers must all lie within it
+    import math
+    import oracle
+    rng = W.make_rng(77)
+    for n in (2, 3, 5, 24, 25, 26, 49, 100, 1000, 4097, 20000):
+        for v in (W.random_permutation(rng, n), rng.integers(0, 3, size=n), np.arange(n)[::-1].copy(),
+                  W.random_runs(rng, n, max(2.0, math.sqrt(n)), 0.25)):
+            ref = oracle.powersort(np.asarray(v).astype(np.int32), None, min_run=w)
+            if ref.powers.size:
+                assert int(ref.powers.max()) <= pass_bound(n, w), (n, w)
+    # and the bound is attained up to one level on a permutation
+    ref = oracle.powersort(W.random_permutation(rng, 1 << 16).astype(np.int32), None, min_run=w)
+    assert int(ref.powers.max()) >= pass_bound(1 << 16, w) - 1
