@@ -71,7 +71,7 @@ constexpr int kFuseItems = 8;
 constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
 // A fused subtree with 4-byte keys and at least this many leaves is sorted
 // by the block radix sort instead of level-by-level merges.
-constexpr uint32_t kFuseRadixMinLeaves = 16;
+constexpr uint32_t kFuseRadixMinLeaves = 8;
 __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nleaves) {
     return key_bytes == 4 && nleaves >= kFuseRadixMinLeaves;
 }

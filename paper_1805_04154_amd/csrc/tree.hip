@@ -16,8 +16,9 @@
 //     P_1..P_i and the right ones the strict prefix minima of P_{i+1}..P_{r-1};
 //     their powers are distinct, so each side is a bit set over powers, and
 //     "drop every power >= p, add p" composes associatively as a pair of
-//     masks (A, B): G -> (G & A) | B.  Two scans give every depth, the buffer
-//     parity of every leaf and node, and M = sum_i depth_i L_i (Sec. 2.3).
+//     masks (A, B): G -> (G & A) | B.  Two scans give every depth (which
+//     places each leaf and node in its data array) and M = sum_i depth_i L_i
+//     (Sec. 2.3).
 //   * ranges: node j of power p merges exactly the leaves whose q share their
 //     top p-1 bits with q_j (the level-(p-1) dyadic cell of Method 2'), a
 //     contiguous block of the sorted Q array found by galloping search.
