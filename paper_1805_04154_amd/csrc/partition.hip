@@ -18,11 +18,13 @@
 // them yields each tile's true entry, and a second pass over the tile emits
 // the leaf starts.
 //
-// Inside a tile the chain is followed in one of three ways: a tile inside
+// Inside a tile the chain is followed in one of four ways: a tile inside
 // one long run jumps straight past its window; a tile with few run changes
 // and segment starts (at most kWalkMax) walks each chain point by point,
-// finding J from short sorted lists of those positions; any other tile
-// resolves J for every position and follows it by pointer jumping.
+// finding J from short sorted lists of those positions; a tile whose natural
+// runs are all shorter than w steps by w (an arithmetic progression); any
+// other tile resolves J for every position and follows it by pointer
+// jumping.
 #include "common.hpp"
 #include "block.hpp"
 #include "internal.hpp"
@@ -39,7 +41,7 @@ constexpr uint16_t kExitBit = 0x8000u;
 
 enum : uint8_t { kAsc = 0, kDesc = 1, kBreak = 2, kUnknown = 3 };
 // How tile_successors left the tile.
-enum : int { kTileTable = 0, kTileUniform = 1, kTileWalk = 2 };
+enum : int { kTileTable = 0, kTileUniform = 1, kTileWalk = 2, kTileDense = 3 };
 
 // First entry above v of the ascending list a[0..n), or kInf.
 __device__ __forceinline__ uint32_t first_above(const uint16_t* a, uint32_t n, uint32_t v) {
@@ -84,6 +86,8 @@ struct PartShared {
 //    window (exit code w);
 //  * kTileWalk when the window holds at most kWalkMax run changes and breaks
 //    together: they are listed in sm.chg / sm.brk, and walk_next gives J;
+//  * kTileDense when no break lies in the window and every natural run
+//    starting in the tile is shorter than w: then J(s) = s + w for every s;
 //  * kTileTable otherwise, with the encoded successor of every position s in
 //    sm.u.pj.nx (aliased by sm.u.em.nx): a tile-local index if J(s) < T1,
 //    else kExitBit | exit code.
@@ -178,9 +182,11 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         if (k < NPW && tp[i] == kBreak) bpos_min = min(bpos_min, k);
         counts += (chg ? (1u << 16) : 0u) + ((k < NPW && tp[i] == kBreak) ? 1u : 0u);
     }
+    uint32_t nbreaks;
     {
         uint32_t tot;
         const uint32_t ex = block_excl_sum(counts, sm.sh, &tot);
+        nbreaks = tot & 0xFFFFu;
         if ((tot >> 16) + (tot & 0xFFFFu) <= kWalkMax) {
             // Few changes and breaks: list them in position order.
             uint32_t oc = ex >> 16, ob = ex & 0xFFFFu;
@@ -215,6 +221,10 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
     // nextb[k] = first k' >= k that is a break.
     uint32_t runc = cex, runb = bex;
     uint32_t nextc[kPairItems], nextb[kPairItems];
+    // Dense tile: every natural run starting in the tile is shorter than w
+    // and the window holds no break, so J(s) = s + w throughout.
+    bool any_long = false;
+    const uint32_t len = T1 - T0;
 #pragma unroll
     for (int i = kPairItems - 1; i >= 0; --i) {
         const uint32_t k = tid * kPairItems + i;
@@ -222,6 +232,20 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         if (k < NPW && k > 0 && tp[i] != sm.pt[k - 1]) runc = k;
         if (k < NPW && tp[i] == kBreak) runb = k;
         nextb[i] = runb;
+        // the run from position T0-1+k (k in [1, len]) ends at T0 + nextc
+        if (k >= 1 && k <= len) {
+            const uint32_t kc = nextc[i];
+            if (kc == kInf || sm.pt[kc] == kUnknown || kc - k + 1 >= w) any_long = true;
+        }
+    }
+    if (__syncthreads_or(any_long) == 0 && nbreaks == 0) {
+        if (tid == 0) {
+            // no break: pair 0 is a real pair, and its run ends at the first change
+            const uint32_t kc = nextc[0];
+            sm.x0 = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : T0 + kc;
+        }
+        __syncthreads();
+        return kTileDense;
     }
 
 #pragma unroll
@@ -330,10 +354,11 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     // registers, waits, then writes them back.  Walk mode follows each
     // candidate's chain below instead.
     const bool walk = (mode == kTileWalk);
+    const bool jump = (mode == kTileTable);
     constexpr int kPJ = kPartTile / kThreads;  // positions per thread
-    for (uint32_t i = threadIdx.x; !walk && i < len; i += kThreads) sm.u.pj.ct[i] = 1;
+    for (uint32_t i = threadIdx.x; jump && i < len; i += kThreads) sm.u.pj.ct[i] = 1;
     __syncthreads();
-    for (int round = 0; !walk && round < 16; ++round) {
+    for (int round = 0; jump && round < 16; ++round) {
         int any = 0;
         uint16_t na[kPJ], nc[kPJ];
 #pragma unroll
@@ -387,6 +412,9 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
                 s = walk_next<KT>(sm, T0, s, w);
             }
             code = (uint8_t)((s != kFar && s - T1 < w) ? (s - T1) : w);
+        } else if (mode == kTileDense) {
+            cnt = (T1 - pos + w - 1) / w;  // pos, pos + w, ... below T1
+            code = (uint8_t)(pos + cnt * w - T1);
         } else {
             const uint16_t e = sm.u.pj.nx[pos - T0];
             code = (uint8_t)(e & 0xFF);
@@ -498,6 +526,16 @@ __global__ __launch_bounds__(kThreads) void part_emit_kernel(
             const uint32_t rank = offs[blockIdx.x];
             if (rank < rcap) starts[rank] = pos;
         }
+        return;
+    }
+    if (rmode == kTileDense) {
+        // the chain steps by w from its entry: starts pos, pos + w, ...
+        const uint32_t pos = (e < w) ? (T0 + e) : R->x0;
+        if (pos >= T1) return;  // also kFar / kInf
+        const uint32_t cnt = (T1 - pos + w - 1) / w;
+        const uint32_t rank0 = offs[blockIdx.x];
+        for (uint32_t q = tid; q < cnt; q += kThreads)
+            if (rank0 + q < rcap) starts[rank0 + q] = pos + q * w;
         return;
     }
     int mode = kTileWalk;
