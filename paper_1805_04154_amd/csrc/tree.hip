@@ -340,66 +340,104 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                                                              Counters* __restrict__ cnt, TreeLists L,
                                                              unsigned long long* __restrict__ prof) {
     using K = Key<KT>;
-    __shared__ uint32_t sh[kWaves];
-    __shared__ uint32_t base_sh;
+    constexpr int kIt = 4;  // boundaries per thread per step
+    __shared__ uint64_t sh64[kWaves];
+    __shared__ uint32_t base_sh[4];
     const uint32_t r = cnt->r;
     auto size_of = [&](uint32_t j) -> uint32_t { return nsize[j]; };
     // profiling element counts, summed per thread and added once per wave
     unsigned long long pr_leaf = 0, pr_fused = 0, pr_merge = 0;
-    for (uint32_t i0 = blockIdx.x * kThreads; i0 < r; i0 += gridDim.x * kThreads) {
-        const uint32_t i = i0 + threadIdx.x;
-        const bool valid = i < r;
-        // ---- node i (boundary between leaves i-1 and i)
-        bool unit_node = false, big_node = false;
-        uint32_t nlf = 0, nrt = 0;
-        if (valid && i >= 1 && P[i] >= 1) {
-            nlf = Lf[i];
-            nrt = Rt[i];
-            const uint32_t sz = nsize[i];
-            if (sz > (uint32_t)kFuse) {
-                big_node = true;
-                pr_merge += sz;
-            } else {
-                const uint32_t pl = P[nlf], pr = P[nrt];
-                const uint32_t par = pl > pr ? nlf : (pr > pl ? nrt : kNone);
-                unit_node = (par == kNone) || size_of(par) > (uint32_t)kFuse;
+    for (uint32_t i0 = blockIdx.x * kThreads * kIt; i0 < r; i0 += gridDim.x * kThreads * kIt) {
+        // flags of node i and leaf i for this thread's kIt indices; the four
+        // lists (big nodes, unit nodes, unit leaves, big leaves) take slots
+        // from one packed block scan and one atomic per list per step
+        uint8_t fl[kIt];
+        uint8_t mode[kIt];
+        uint32_t nlf[kIt], nrt[kIt];
+        uint64_t mine = 0;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const uint32_t i = i0 + it * kThreads + threadIdx.x;
+            const bool valid = i < r;
+            uint8_t f = 0;
+            mode[it] = kLeafNoop;
+            nlf[it] = nrt[it] = 0;
+            // ---- node i (boundary between leaves i-1 and i)
+            if (valid && i >= 1 && P[i] >= 1) {
+                nlf[it] = Lf[i];
+                nrt[it] = Rt[i];
+                const uint32_t sz = nsize[i];
+                if (sz > (uint32_t)kFuse) {
+                    f |= 1;  // big node
+                    pr_merge += sz;
+                } else {
+                    const uint32_t pl = P[nlf[it]], pr = P[nrt[it]];
+                    const uint32_t par = pl > pr ? nlf[it] : (pr > pl ? nrt[it] : kNone);
+                    if ((par == kNone) || size_of(par) > (uint32_t)kFuse) f |= 2;  // unit node
+                }
+            }
+            // ---- leaf i
+            if (valid) {
+                const uint32_t s = starts[i], len = starts[i + 1] - s;
+                const uint32_t pl = P[i], pr = P[i + 1];
+                const uint32_t par = pl > pr ? i : (pr > pl ? i + 1 : kNone);
+                if (len > (uint32_t)kFuse) {
+                    f |= 8;  // big leaf
+                    const bool desc = K::ord(keys[s + 1]) < K::ord(keys[s]);
+                    const bool moved = big_leaf_buf(leaf_depth[i], L.nbuf) != 0;
+                    mode[it] = desc ? (moved ? kLeafRevCopy : kLeafRevInPlace) : (moved ? kLeafCopy : kLeafNoop);
+                } else if ((par == kNone) || size_of(par) > (uint32_t)kFuse) {
+                    f |= 4;  // unit leaf
+                }
+            }
+            fl[it] = f;
+            mine += (uint64_t)(f & 1) + ((uint64_t)((f >> 1) & 1) << 16) + ((uint64_t)((f >> 2) & 1) << 32) +
+                    ((uint64_t)((f >> 3) & 1) << 48);
+        }
+        uint64_t total;
+        uint64_t off = block_excl_sum64(mine, sh64, &total);
+        if (threadIdx.x < 4) {
+            const uint32_t c = (uint32_t)(total >> (16 * threadIdx.x)) & 0xFFFFu;
+            uint32_t* ctr = threadIdx.x == 0 ? &cnt->nbig : threadIdx.x == 1 ? &cnt->nunits
+                          : threadIdx.x == 2 ? &cnt->nunits : &cnt->nbigleaf;
+            // unit nodes and unit leaves share one list: reserve both from
+            // thread 1, in that order
+            if (threadIdx.x == 1) {
+                const uint32_t cl = (uint32_t)(total >> 32) & 0xFFFFu;
+                base_sh[1] = (c + cl) ? atomicAdd(ctr, c + cl) : 0u;
+                base_sh[2] = base_sh[1] + c;
+            } else if (threadIdx.x != 2) {
+                base_sh[threadIdx.x] = c ? atomicAdd(ctr, c) : 0u;
             }
         }
-        uint32_t slot = block_append(big_node, &cnt->nbig, sh, &base_sh);
-        if (big_node) L.biglist[slot] = i;
-        slot = block_append(unit_node, &cnt->nunits, sh, &base_sh);
-        if (unit_node) {
-            pr_fused += starts[nrt] - starts[nlf];
-            L.unit_rec[slot] = UnitRec{nlf, nrt, starts[nlf], starts[nrt]};
-            L.unit_par[slot] = node_buf(node_depth[i], L.nbuf);
-        }
-        // ---- leaf i
-        bool unit_leaf = false, big_leaf = false;
-        uint8_t mode = kLeafNoop;
-        if (valid) {
-            const uint32_t s = starts[i], len = starts[i + 1] - s;
-            const uint32_t pl = P[i], pr = P[i + 1];
-            const uint32_t par = pl > pr ? i : (pr > pl ? i + 1 : kNone);
-            if (len > (uint32_t)kFuse) {
-                big_leaf = true;
-                const bool desc = K::ord(keys[s + 1]) < K::ord(keys[s]);
-                const bool moved = big_leaf_buf(leaf_depth[i], L.nbuf) != 0;
-                mode = desc ? (moved ? kLeafRevCopy : kLeafRevInPlace) : (moved ? kLeafCopy : kLeafNoop);
-            } else {
-                unit_leaf = (par == kNone) || size_of(par) > (uint32_t)kFuse;
+        __syncthreads();
+        uint32_t pos[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pos[q] = base_sh[q] + ((uint32_t)(off >> (16 * q)) & 0xFFFFu);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const uint32_t i = i0 + it * kThreads + threadIdx.x;
+            const uint8_t f = fl[it];
+            if (f & 1) L.biglist[pos[0]++] = i;
+            if (f & 2) {
+                const uint32_t slot = pos[1]++;
+                pr_fused += starts[nrt[it]] - starts[nlf[it]];
+                L.unit_rec[slot] = UnitRec{nlf[it], nrt[it], starts[nlf[it]], starts[nrt[it]]};
+                L.unit_par[slot] = node_buf(node_depth[i], L.nbuf);
             }
-        }
-        slot = block_append(unit_leaf, &cnt->nunits, sh, &base_sh);
-        if (unit_leaf) {
-            pr_fused += starts[i + 1] - starts[i];
-            L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
-            L.unit_par[slot] = node_buf(leaf_depth[i], L.nbuf);
-        }
-        slot = block_append(big_leaf, &cnt->nbigleaf, sh, &base_sh);
-        if (big_leaf) {
-            if (mode != kLeafNoop) pr_leaf += starts[i + 1] - starts[i];
-            L.bigleaf[slot] = i;
-            L.bigleaf_mode[slot] = mode;
+            if (f & 4) {
+                const uint32_t slot = pos[2]++;
+                pr_fused += starts[i + 1] - starts[i];
+                L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
+                L.unit_par[slot] = node_buf(leaf_depth[i], L.nbuf);
+            }
+            if (f & 8) {
+                const uint32_t slot = pos[3]++;
+                if (mode[it] != kLeafNoop) pr_leaf += starts[i + 1] - starts[i];
+                L.bigleaf[slot] = i;
+                L.bigleaf_mode[slot] = mode[it];
+            }
         }
     }
     if (prof) {
@@ -736,8 +774,8 @@ hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_tree_lists(int kt, const TreeArgs& a, hipStream_t st) {
-    // fewer blocks: each block_append is one atomic per block on a shared counter
-    const uint32_t gl = grid_for(a.rmax, 1024);
+    // fewer blocks: each step of a block is one atomic per list on a shared counter
+    const uint32_t gl = grid_for((a.rmax + 3) / 4, 1024);
     switch (kt) {
     case KT_I32: launch_classify_t<KT_I32>(a, gl, st); break;
     case KT_U32: launch_classify_t<KT_U32>(a, gl, st); break;
