@@ -75,7 +75,6 @@ struct PartShared {
     uint32_t sh[2 * kWaves];
     uint32_t gfirst;
     uint32_t x0;                              // end of the run crossing T0 (kFar / kInf)
-    int flag;
 };
 
 // Classifies pairs of tile [T0, T1) and its window and sets sm.x0, the end of

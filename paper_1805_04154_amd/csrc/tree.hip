@@ -315,17 +315,6 @@ __device__ __forceinline__ uint32_t block_append(bool pred, uint32_t* counter, u
     return pred ? base + pos : kNone;
 }
 
-__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t m = __ballot(pred);
-    if (!m) return kNone;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    return pred ? base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)) : kNone;
-}
-
 // Classify leaves and nodes: fused-subtree roots (maximal subtrees of at most
 // kFuse elements), leaves longer than kFuse, and big nodes (counted per power).
 template <int KT>
