@@ -600,7 +600,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         e = stage(PS_PROF_BIG_LEAF, 0, 0, tune.grid_big_leaf);
         if (e == hipSuccess) e = stage(PS_PROF_FUSED, 5, 0, grid_fuse);  // single-run units
         if (e == hipSuccess) e = stage(PS_PROF_FUSED, 1, 0, grid_fuse);
-        if (e == hipSuccess && key_bytes(c.kt) == 4) e = stage(PS_PROF_FUSED, 4, 0, grid_fuse);
+        if (e == hipSuccess) e = stage(PS_PROF_FUSED, 4, 0, grid_fuse);
         for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
             e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);  // tile co-ranks of pass p
             if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);

@@ -69,11 +69,12 @@ constexpr int kFuseThreads = 512;
 constexpr int kFuseWaves = kFuseThreads / 64;
 constexpr int kFuseItems = 8;
 constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
-// A fused subtree with 4-byte keys and at least this many leaves is sorted
-// by the block radix sort instead of level-by-level merges.
+// A fused subtree with at least this many leaves is sorted by the block
+// radix sort instead of level-by-level merges (any key width: 8-byte keys
+// need 108 KiB of LDS, one block per CU, and still win on permutations).
 constexpr uint32_t kFuseRadixMinLeaves = 8;
 __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nleaves) {
-    return key_bytes == 4 && nleaves >= kFuseRadixMinLeaves;
+    return (key_bytes == 4 || key_bytes == 8) && nleaves >= kFuseRadixMinLeaves;
 }
 // Leaves in a subtree of kFuse elements: at most kFuse / w + 1 (all but the
 // last leaf of a segment hold >= w elements; natural runs hold >= 2).

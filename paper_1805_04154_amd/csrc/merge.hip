@@ -253,7 +253,7 @@ __host__ __device__ constexpr uint32_t radix_lds_bytes(uint32_t key_bytes, bool 
     return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2 + kFuse * 2;
 }
 
-// Fused subtrees with many leaves (4-byte keys): every merge in a subtree is
+// Fused subtrees with many leaves: every merge in a subtree is
 // stable and takes the left run first, so its result is the stable sort of
 // its original elements, which the block radix sort computes in a fixed
 // number of passes instead of one pass per tree level.
@@ -760,7 +760,6 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
     else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
-        if (kb != 4) return;  // only 4-byte keys take the radix path
         static bool rattr_set = false;
         if (!rattr_set) {
             (void)hipFuncSetAttribute((const void*)fused_radix_kernel<KT, HP>,
@@ -786,10 +785,10 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
     else launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
 }
 
-// stage 0: big leaves; 1: fused subtrees (level by level); 4: fused
-// subtrees by radix sort (4-byte keys, many leaves; no launch otherwise);
-// 2: the merge pass of power p; 3: the split pass of power p.  ev0 / ev1:
-// optional dispatch events.
+// stage 0: big leaves; 5: single-run fused units (copied); 1: fused
+// subtrees (level by level); 4: fused subtrees with many leaves (radix
+// sort); 2: the merge pass of power p; 3: the split pass of power p.
+// ev0 / ev1: optional dispatch events.
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define PS_STAGE(KTV)                                                            \
