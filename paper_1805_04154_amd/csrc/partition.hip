@@ -216,51 +216,30 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
     }
     const uint32_t cex = block_excl_suffix_min(cpos_min, sm.sh);
     const uint32_t bex = block_excl_suffix_min(bpos_min, sm.sh + kWaves);
-    // Right-to-left: nextc[k] = first k' > k where the pair type changes,
-    // nextb[k] = first k' >= k that is a break.
     uint32_t runc = cex, runb = bex;
-    uint32_t nextc[kPairItems], nextb[kPairItems];
-    // Dense tile: every natural run starting in the tile is shorter than w
-    // and the window holds no break, so J(s) = s + w throughout.
+    // One right-to-left pass gives, for every pair k of this thread, the next
+    // type change after k (runc) and the next break at or after k (runb), and
+    // with them the successor J of position T0-1+k, written to nx.  It also
+    // decides the dense case: every natural run starting in the tile shorter
+    // than w and no break in the window, so J(s) = s + w throughout (then nx
+    // is not used).
     bool any_long = false;
     const uint32_t len = T1 - T0;
 #pragma unroll
     for (int i = kPairItems - 1; i >= 0; --i) {
         const uint32_t k = tid * kPairItems + i;
-        nextc[i] = runc;
+        const uint32_t kc = runc;  // first change after k
         if (k < NPW && k > 0 && tp[i] != sm.pt[k - 1]) runc = k;
         if (k < NPW && tp[i] == kBreak) runb = k;
-        nextb[i] = runb;
-        // the run from position T0-1+k (k in [1, len]) ends at T0 + nextc
-        if (k >= 1 && k <= len) {
-            const uint32_t kc = nextc[i];
-            if (kc == kInf || sm.pt[kc] == kUnknown || kc - k + 1 >= w) any_long = true;
-        }
-    }
-    if (__syncthreads_or(any_long) == 0 && nbreaks == 0) {
-        if (tid == 0) {
-            // no break: pair 0 is a real pair, and its run ends at the first change
-            const uint32_t kc = nextc[0];
-            sm.x0 = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : T0 + kc;
-        }
-        __syncthreads();
-        return kTileDense;
-    }
-
-#pragma unroll
-    for (int i = 0; i < kPairItems; ++i) {
-        const uint32_t k = tid * kPairItems + i;
+        const uint32_t kb = runb;  // first break at or after k
         if (k >= NPW) continue;
+        // the run from position T0-1+k (k in [1, len]) ends at T0 + kc
+        if (k >= 1 && k <= len && (kc == kInf || sm.pt[kc] == kUnknown || kc - k + 1 >= w)) any_long = true;
         // End of the run containing pair k, as a position (kFar if unknown).
         uint32_t ne;
-        if (tp[i] == kBreak) {
-            ne = T0 + k;  // the run starting at T0-1+k is that single element
-        } else if (tp[i] == kUnknown) {
-            ne = kFar;
-        } else {
-            const uint32_t kc = nextc[i];
-            ne = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : (T0 + kc);
-        }
+        if (tp[i] == kBreak) ne = T0 + k;  // the run starting at T0-1+k is that single element
+        else if (tp[i] == kUnknown) ne = kFar;
+        else ne = (kc == kInf || sm.pt[kc] == kUnknown) ? kFar : (T0 + kc);
         if (k == 0) {
             // Run crossing T0: only a real (non-break) pair (T0-1, T0) crosses.
             sm.x0 = (tp[i] == kBreak) ? kInf : ne;
@@ -268,7 +247,7 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         }
         const uint32_t s = T0 - 1 + k;
         if (s >= T1) continue;
-        const uint32_t seg_end = (nextb[i] == kInf) ? kFar : (T0 + nextb[i]);
+        const uint32_t seg_end = (kb == kInf) ? kFar : (T0 + kb);
         uint32_t J;
         if (ne == kFar) J = kFar;
         else if (ne - s >= w) J = ne;
@@ -278,8 +257,9 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         else enc = kExitBit | (uint16_t)((J != kFar && J - T1 < w) ? (J - T1) : w);
         sm.u.pj.nx[s - T0] = enc;
     }
-    __syncthreads();
-    return kTileTable;
+    // the block-wide OR is also the barrier after every nx and x0 write
+    const bool dense = __syncthreads_or(any_long) == 0 && nbreaks == 0;
+    return dense ? kTileDense : kTileTable;
 }
 
 // J(s) for a position s in [T0, T1) of a tile in walk mode: the same rule as
