@@ -72,6 +72,7 @@ struct PartShared {
     uint16_t brk[kWalkMax];                   // walk: pairs k of type kBreak
     uint8_t ctype[kWalkMax];                  // walk (emit): type of pair chg[i]
     uint32_t nchg, nbrk;
+    uint32_t dirs;                            // OR of the directions seen: 1 ascending, 2 descending
     uint32_t sh[2 * kWaves];
     uint32_t gfirst;
     uint32_t x0;                              // end of the run crossing T0 (kFar / kInf)
@@ -119,45 +120,57 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
 #pragma unroll
             for (int i = 0; i < kPairItems; ++i) sm.edge[wv][i] = K::ord(kv[i]);
         }
-        if (tid == 0 && nseg > 1) sm.gfirst = tile_seg[T0 / kPartTile];  // first offset >= T0
+        if (tid == 0) {
+            if (nseg > 1) sm.gfirst = tile_seg[T0 / kPartTile];  // first offset >= T0
+            sm.dirs = 0;
+        }
         __syncthreads();
-        bool any_asc = false, any_desc = false;
+        // pair types of this thread's pairs, 2 bits each, kept in registers
+        // until the tile is known not to lie inside one run
+        uint64_t types = 0;
+        uint32_t dirs = 0;
 #pragma unroll
         for (int i = 0; i < kPairItems; ++i) {
             const uint32_t k = tid + i * kThreads;
             const U u = K::ord(kv[i]);
             U v = __shfl_down(u, 1);
             if (lane == 63) v = (wv + 1 < kWaves) ? sm.edge[wv + 1][i] : sm.edge[0][i + 1];
-            if (k < NPW) {
-                uint8_t t;
-                if (k == 0 && T0 == 0) {
-                    t = kBreak;                                  // nothing left of position 0
-                } else if (k + 1 < NPW) {
-                    t = (v < u) ? kDesc : kAsc;
-                    if (k >= 1) {
-                        any_desc |= (t == kDesc);
-                        any_asc |= (t == kAsc);
-                    }
-                } else {
-                    t = (WE == N) ? kBreak : kUnknown;           // pair (WE-1, WE)
-                }
-                sm.pt[k] = t;
+            uint32_t t;
+            if (k == 0 && T0 == 0) {
+                t = kBreak;                                  // nothing left of position 0
+            } else if (k + 1 < NPW) {
+                t = (v < u) ? kDesc : kAsc;
+                if (k >= 1) dirs |= (t == kDesc) ? 2u : 1u;
+            } else {
+                t = (WE == N) ? kBreak : kUnknown;           // pair (WE-1, WE)
             }
+            types |= (uint64_t)t << (2 * i);
         }
+        // one LDS word gathers the directions: a wave OR, then one atomic per wave
+        const uint32_t wdirs = (__ballot(dirs & 1u) ? 1u : 0u) | (__ballot(dirs & 2u) ? 2u : 0u);
+        if (lane == 0 && wdirs) atomicOr(&sm.dirs, wdirs);
+        __syncthreads();
         // Inside one long run?  Every pair 1..NPW-2 has one direction, the
         // window ends before N, and no segment starts inside it.
+        const uint32_t all = sm.dirs;
         const bool seg_inside = nseg > 1 && sm.gfirst <= nseg && offsets[sm.gfirst] <= (uint64_t)WE;
-        const bool asc = __syncthreads_or(any_asc), desc = __syncthreads_or(any_desc);
-        if (asc != desc && WE < N && !seg_inside) {
+        if ((all == 1u || all == 2u) && WE < N && !seg_inside) {
             if (tid == 0) {
                 // the run through pair (T0-1, T0) either continues (same
                 // direction), or does not exist (a break), or ends at T0
-                const uint8_t t0 = sm.pt[0], t1 = desc ? (uint8_t)kDesc : (uint8_t)kAsc;
+                const uint8_t t0 = (uint8_t)(types & 3u), t1 = (all == 2u) ? (uint8_t)kDesc : (uint8_t)kAsc;
+                sm.pt[0] = t0;
                 sm.x0 = (t0 == t1) ? kFar : (t0 == kBreak ? kInf : T0 + 1);
             }
             __syncthreads();
             return kTileUniform;
         }
+#pragma unroll
+        for (int i = 0; i < kPairItems; ++i) {
+            const uint32_t k = tid + i * kThreads;
+            if (k < NPW) sm.pt[k] = (uint8_t)((types >> (2 * i)) & 3u);
+        }
+        __syncthreads();
     }
     // A segment start o in (T0-1, WE] breaks pair o-1: runs never cross it.
     // (With one segment the only starts are 0 and N, handled above.)
