@@ -142,8 +142,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the sort is single-device with no sharding or collectives", file=sys.stderr)
+        print(f"bench.py: the sort runs on one GPU (asked for --gpus {args.gpus}); "
+              "it has no sharding or collectives", file=sys.stderr)
         return 2
     if args.workload == "batched":
         return run_batched(args)

@@ -602,7 +602,9 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         if (e == hipSuccess) e = stage(PS_PROF_FUSED, 1, 0, grid_fuse);
         if (e == hipSuccess) e = stage(PS_PROF_FUSED, 4, 0, grid_fuse);
         for (uint32_t p = pmax; p >= 1 && e == hipSuccess; --p) {
-            e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);  // tile co-ranks of pass p
+            // tile co-ranks: a split pass for 4-byte keys; 8-byte keys find
+            // them inside the merge pass
+            if (kb == 4) e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);
             if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");

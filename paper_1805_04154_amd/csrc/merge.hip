@@ -626,6 +626,162 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
     }
 }
 
+// One merge-path tile of merge_pass_cr_kernel: tile t of the pass belongs
+// to bucket entry `node`; i0 is the co-rank at its start and i1n the one at
+// the next tile's start (used when that tile is in the same node).  NT
+// threads x IT outputs.
+template <int KT, bool HP, int NT, int IT>
+__device__ __forceinline__ void merge_tile(const MoveArgs& a, MergeShared<KT, NT * IT>& sm, uint32_t node,
+                                           uint32_t t, uint32_t i0, uint32_t i1n) {
+    constexpr int TILE = NT * IT;
+    using K = Key<KT>;
+    using U = typename K::ukey;
+    using raw = typename K::raw;
+    const int tid = threadIdx.x;
+    const NodeRec R = a.node_rec[node];
+    const uint32_t tt = t - a.bucket_tile[node];
+    const uint32_t lo = R.lo, mid = R.mid, hi = R.hi;
+    const uint32_t bufs = R.bufs;
+    const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + lo;
+    const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 4) & 3u) + mid;
+    raw* dst = (raw*)pick3u(a.keys, bufs & 3u);
+    const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + lo;
+    const uint32_t* psrcB = pick3u(a.pay, (bufs >> 4) & 3u) + mid;
+    uint32_t* pdst = pick3u(a.pay, bufs & 3u);
+    const uint32_t la = mid - lo, tot = hi - lo;
+    const uint32_t k0 = tt * TILE, k1 = min(tot, k0 + TILE);
+    const uint32_t i1 = (k1 == tot) ? la : i1n;  // the next tile is in this node
+    const uint32_t j0 = k0 - i0, j1 = k1 - i1;
+    const uint32_t na = i1 - i0, nbb = j1 - j0, nt = na + nbb;
+    U kr[IT];
+    uint32_t pr[IT];
+    {
+        raw kv[IT];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t x = tid + i * NT;
+            // two masked loads with scalar bases (not a per-lane
+            // pointer select, which costs 64-bit address arithmetic)
+            if (x < na) {
+                kv[i] = srcA[i0 + x];
+                if (HP) pr[i] = psrcA[i0 + x];
+            } else if (x < nt) {
+                kv[i] = srcB[j0 + x - na];
+                if (HP) pr[i] = psrcB[j0 + x - na];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t x = tid + i * NT;
+            if (x < nt) {
+                sm.sk[x] = K::ord(kv[i]);
+                if (HP) sm.sp[x] = pr[i];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t dx = tid * IT;
+    if (dx < nt) {
+        uint32_t l = dx > nbb ? dx - nbb : 0, h = min(dx, na);
+        while (l < h) {
+            const uint32_t m = (l + h) >> 1;
+            if (sm.sk[m] <= sm.sk[na + dx - 1 - m]) l = m + 1; else h = m;
+        }
+        uint32_t ia = l, ib = na + (dx - l);
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            if (dx + i < nt) {
+                const bool take_a = (ib >= nt) || (ia < na && sm.sk[ia] <= sm.sk[ib]);
+                const uint32_t s = take_a ? ia++ : ib++;
+                kr[i] = sm.sk[s];
+                if (HP) pr[i] = sm.sp[s];
+            }
+        }
+    }
+    __syncthreads();
+    if (dx < nt) {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            if (dx + i < nt) {
+                sm.sk[dx + i] = kr[i];
+                if (HP) sm.sp[dx + i] = pr[i];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t x = tid + i * NT;
+        if (x < nt) {
+            kr[i] = sm.sk[x];
+            if (HP) pr[i] = sm.sp[x];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t x = tid + i * NT;
+        if (x < nt) {
+            dst[lo + k0 + x] = K::unord(kr[i]);
+            if (HP) pdst[lo + k0 + x] = pr[i];
+        }
+    }
+    __syncthreads();
+}
+
+// Merge pass for 8-byte keys: a workgroup owns a contiguous run of tiles
+// and finds their co-ranks itself (no split pass).  NT threads x IT outputs
+// per tile.  4-byte keys keep merge_pass_kernel below with the split pass's
+// records: there the grid-stride tile order measured faster, and its tile
+// body is kept inline as it was (the shared merge_tile body compiled 3%
+// slower for them).
+template <int KT, bool HP, int NT, int IT>
+__global__ __launch_bounds__(NT) void merge_pass_cr_kernel(MoveArgs a, uint32_t p) {
+    constexpr int TILE = NT * IT;
+    using K = Key<KT>;
+    using raw = typename K::raw;
+    __shared__ MergeShared<KT, TILE> sm;
+    const int tid = threadIdx.x;
+    __shared__ uint32_t cr[NT + 1];   // co-rank at the start of each tile of the step (and of the next tile)
+    __shared__ uint32_t crn[NT + 1];  // its node (bucket entry)
+    const uint32_t ntiles = a.cnt->ptiles[p];
+    const uint32_t nb = a.cnt->pcount[p];
+    const uint32_t bbase = a.cnt->pbase[p];
+    if (nb == 0 || ntiles == 0) return;
+    // A workgroup owns a contiguous run of tiles.  It finds the co-ranks
+    // of their starts itself, one lane per tile, up to NT tiles per step:
+    // the searches of workgroups that start later overlap the merging of
+    // others.
+    const uint32_t chunk = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t tb = min(ntiles, blockIdx.x * chunk), te = min(ntiles, tb + chunk);
+    for (uint32_t s0 = tb; s0 < te; s0 += NT) {
+        const uint32_t s1 = min(te, s0 + NT);
+        // Co-rank of diagonal d in the stable merge of A = [lo, mid) and
+        // B = [mid, hi): the number of A elements among the first d
+        // outputs, A going first on equal keys, by binary search.  Entry
+        // s1 - s0 is the next tile's start, the end of tile s1 - 1.
+        for (uint32_t j = tid; j <= s1 - s0; j += NT) {
+            const uint32_t t = s0 + j;
+            if (t >= ntiles) continue;
+            const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
+            const NodeRec Rk = a.node_rec[bbase + k];
+            const raw* A = (const raw*)pick3(a.keys, (Rk.bufs >> 2) & 3u) + Rk.lo;
+            const raw* B = (const raw*)pick3(a.keys, (Rk.bufs >> 4) & 3u) + Rk.mid;
+            const uint32_t la = Rk.mid - Rk.lo, lb = Rk.hi - Rk.mid;
+            const uint32_t d = (t - a.bucket_tile[bbase + k]) * TILE;
+            uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
+            while (l < h) {
+                const uint32_t m = (l + h) >> 1;
+                if (K::ord(A[m]) <= K::ord(B[d - 1 - m])) l = m + 1; else h = m;
+            }
+            cr[j] = l;
+            crn[j] = bbase + k;
+        }
+        __syncthreads();
+        for (uint32_t t = s0; t < s1; ++t)
+            merge_tile<KT, HP, NT, IT>(a, sm, crn[t - s0], t, cr[t - s0], cr[t - s0 + 1]);
+    }
+}
+
 // NT threads x IT outputs per tile (the tile size a.merge_tile).
 template <int KT, bool HP, int NT, int IT>
 __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) {
@@ -771,12 +927,12 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
     else if (stage == 2) {
         constexpr bool wide = sizeof(typename Key<KT>::ukey) == 8;
         if (a.merge_tile == 2048) {
-            if constexpr (wide) launch(merge_pass_kernel<KT, HP, 512, 4>, grid, 512, 0, st, ev0, ev1, a, p);
+            if constexpr (wide) launch(merge_pass_cr_kernel<KT, HP, 512, 4>, grid, 512, 0, st, ev0, ev1, a, p);
             else launch(merge_pass_kernel<KT, HP, 256, 8>, grid, 256, 0, st, ev0, ev1, a, p);
         } else if (a.merge_tile == 4096) {
             // 8-byte keys: more, lighter threads per tile (2^28 uint64 Zipf:
             // merge passes 7.97 -> 7.06 ms); 4-byte keys keep 8 per thread
-            if constexpr (wide) launch(merge_pass_kernel<KT, HP, 1024, 4>, grid, 1024, 0, st, ev0, ev1, a, p);
+            if constexpr (wide) launch(merge_pass_cr_kernel<KT, HP, 1024, 4>, grid, 1024, 0, st, ev0, ev1, a, p);
             else launch(merge_pass_kernel<KT, HP, 512, 8>, grid, 512, 0, st, ev0, ev1, a, p);
         }
         else if constexpr (sizeof(typename Key<KT>::ukey) == 4)  // 8192: 64 KiB of LDS, 4-byte keys only
