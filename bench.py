@@ -74,11 +74,11 @@ def merge_kernel_digest() -> str:
     return hashlib.sha256((src[a:a2] + src[b:b2]).encode()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, launches_per_sort: int):
+def measured_traffic(workload: str, launches_per_sort: int, merge_tile: int):
     """HBM bytes per merge-pass launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated against a device copy), if
-    it was taken on this workload, on the current kernel source and with the
-    same number of merge launches per sort; else None."""
+    it was taken on this workload, on the current kernel source, with the
+    same merge tile and number of merge launches per sort; else None."""
     try:
         text = open(COUNTERS_MD).read()
     except OSError:
@@ -91,6 +91,8 @@ def measured_traffic(workload: str, launches_per_sort: int):
     if fields.get("workload") != workload or fields.get("kernel_source_digest") != merge_kernel_digest():
         return None
     if fields.get("merge_launches_per_sort") != str(launches_per_sort):
+        return None
+    if fields.get("merge_tile") != str(merge_tile):
         return None
     try:
         return int(fields["hbm_bytes_per_launch"])
@@ -248,11 +250,17 @@ def main() -> int:
     achieved_gbs = (mp_bytes_per_launch / (mp_launch_ms / 1e3)) / 1e9 if mp_launch_ms > 0 else 0.0
     peak_gbs = HBM_PEAK_BPS / 1e9
     launches_per_sort = mp["launches"] // max(args.steps, 1)
-    traffic = (measured_traffic(wl.name, launches_per_sort) if (args.min_run == 24 and args.method == "powersort")
-               else None)
+    # 8192-output tiles apply to 4-byte keys only; 8-byte keys merge with
+    # 4096-output tiles in the kernel that finds its own co-ranks
+    merge_tile = binding.get_tuning()["merge_tile"]
+    if kb == 8:
+        merge_tile = min(merge_tile, 4096)
+    traffic = (measured_traffic(wl.name, launches_per_sort, merge_tile)
+               if (args.min_run == 24 and args.method == "powersort") else None)
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": peak_gbs, "unit": "GB/s",
                 "frac": round(achieved_gbs / peak_gbs, 4), "traffic": traffic,
-                "kernel": "merge_pass_kernel", "launch_ms": round(mp_launch_ms, 4),
+                "kernel": "merge_pass_kernel" if kb == 4 else "merge_pass_cr_kernel",
+                "merge_tile": merge_tile, "launch_ms": round(mp_launch_ms, 4),
                 "algorithmic_bytes_per_launch": int(mp_bytes_per_launch)}
     # Whole path: B_alg = (K+V)(2M + 2n) per sort, from the merge cost.
     b_alg = rec_bytes * (2 * merge_cost + 2 * n)

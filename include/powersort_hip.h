@@ -176,6 +176,8 @@ ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uin
  * changes only speed, never results: grids are workgroup counts of
  * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048,
  * 4096 or 8192 (8192 applies to 4-byte keys; 8-byte keys then use 4096).
+ * Defaults: merge_tile 8192, grid_merge 2048, grid_split 512, grid_fused
+ * 2048, grid_big_leaf 2048.
  * Zero fields keep their current value.  Written by the project's
  * autotuner for a workload; read back with ps_get_tuning. */
 typedef struct {

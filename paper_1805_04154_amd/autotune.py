@@ -1,7 +1,7 @@
 """Autotuner for the launch shape of the data-movement kernels.
 
 The tunables (``ps_tuning``) change speed only, never results: the grid sizes
-of the grid-stride kernels and the merge-path tile (2048 or 4096 outputs).
+of the grid-stride kernels and the merge-path tile (2048, 4096 or 8192 outputs).
 ``tune()`` times every candidate on a caller-supplied step (which must
 restore its own input before sorting), keeps the fastest, and records it in a
 JSON cache keyed by a workload signature so later runs start from the tuned
@@ -22,7 +22,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "powersort_hip",
 
 def candidates(small: bool = False) -> list[dict]:
     """The search space: merge tile x merge grid x fused grid x split grid."""
-    tiles = (4096, 2048, 8192)
+    tiles = (8192, 4096, 2048)
     merge_grids = (1024, 2048, 4096) if not small else (2048,)
     fused_grids = (1024, 2048) if not small else (2048,)
     split_grids = (256, 512, 1024) if not small else (512,)

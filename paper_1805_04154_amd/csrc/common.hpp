@@ -80,10 +80,11 @@ __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nl
 // last leaf of a segment hold >= w elements; natural runs hold >= 2).
 __host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFuse / (w < 2 ? 2 : w) + 1; }
 
-// Global merge passes: merge-path tiles of 4096 outputs (512 threads x 8)
-// by default; 2048 (256 x 8) or, for 4-byte keys, 8192 (1024 x 8) when
-// tuned so.
-constexpr uint32_t kMergeTileDefault = 4096;
+// Global merge passes: merge-path tiles of 8192 outputs (1024 threads x 8)
+// by default for 4-byte keys, which halves the split searches; 8-byte keys
+// use 4096 (1024 x 4) in place of 8192.  2048 and 4096 can be tuned for
+// either.
+constexpr uint32_t kMergeTileDefault = 8192;
 constexpr uint32_t kMergeTileMin = 2048;
 
 // Copy/reverse of leaves longer than kFuse.

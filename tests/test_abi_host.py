@@ -90,7 +90,7 @@ def test_tuning_roundtrip_on_host():
     from paper_1805_04154_amd import binding
     binding.set_tuning(None)
     d = binding.get_tuning()
-    assert d["merge_tile"] == 4096
+    assert d["merge_tile"] == 8192
     binding.set_tuning({"merge_tile": 2048, "grid_merge": 333})
     d2 = binding.get_tuning()
     assert d2["merge_tile"] == 2048 and d2["grid_merge"] == 333 and d2["grid_fused"] == d["grid_fused"]
