@@ -11,7 +11,11 @@ Prints one JSON line (rank 0) with keys/s, the HBM roofline of the merge-pass
 kernel, the whole-path fraction of the roofline computed from the merge cost,
 and the CPU oracle timed on the host as a reported baseline.
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+Three more regions of the same sorts are reported for information: with no
+events at all, with every kernel group timed, and with one event between
+consecutive sorts (median, p10 and p90 of the per-sort time).
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 5]
 """
 from __future__ import annotations
 
@@ -118,14 +122,34 @@ def cpu_baseline(wl, budget_s: float, method: str = "powersort") -> dict:
         dt = time.perf_counter() - t
     return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} of the {n} keys of the same workload (payload = index), one {method} call, "
-                      f"single thread on the host CPU ({os.cpu_count()} logical cores visible), {dt:.2f} s"}
+                      f"single thread on the host CPU ({host_cpu()}, {os.cpu_count()} logical cores visible), "
+                      f"{dt:.2f} s"}
+
+
+def host_cpu() -> str:
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def percentiles_ms(samples_s) -> dict:
+    """Median, p10 and p90 of per-sort durations, in ms."""
+    a = np.sort(np.asarray(samples_s, dtype=np.float64)) * 1e3
+    return {"median": round(float(np.median(a)), 4), "p10": round(float(np.percentile(a, 10)), 4),
+            "p90": round(float(np.percentile(a, 90)), 4), "sorts": int(a.size)}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--workload", choices=WORKLOADS, default="zipf_i32")
     ap.add_argument("--min-run", type=int, default=24)
@@ -180,25 +204,30 @@ def main() -> int:
             p.copy_(src_p)
         torch.cuda.synchronize()
 
-    def region(groups):
+    def region(groups, per_sort=False):
         """Sort every copy back to back; groups: kernel groups timed with
-        HIP events on the sort's stream (None: no events at all)."""
+        HIP events on the sort's stream (None: no events at all).  With
+        per_sort, an event between consecutive sorts gives each one's
+        duration (returned in place of the total)."""
         refill()
         binding.profile_enable(groups is not None, groups=groups if groups else None)
         binding.profile_read(reset=True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(copies) + 1 if per_sort else 2)]
         torch.cuda.synchronize()
         t_a = time.perf_counter()
-        e0.record(stream)
-        for k, p in copies:
+        ev[0].record(stream)
+        for i, (k, p) in enumerate(copies):
             binding.sort(k, p, min_run=args.min_run, merge_cost=M, method=args.method)
-        e1.record(stream)
+            if per_sort:
+                ev[i + 1].record(stream)
+        ev[-1].record(stream)
         torch.cuda.synchronize()
         t_b = time.perf_counter()
         pr = binding.profile_read(reset=True) if groups is not None else None
         binding.profile_enable(False)
-        return t_b - t_a, e0.elapsed_time(e1) / 1e3, pr
+        if per_sort:
+            return t_b - t_a, [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(len(copies))], pr
+        return t_b - t_a, ev[0].elapsed_time(ev[-1]) / 1e3, pr
 
     for i in range(args.warmup):
         k, p = copies[i % len(copies)]
@@ -216,6 +245,7 @@ def main() -> int:
     # Informational: the same steps without any events, and with every group timed.
     plain_s, _, _ = region(None)
     _, _, prof_all = region(tuple(binding.PROF_GROUPS))
+    _, per_sort_s, _ = region(None, per_sort=True)
     step_s = wall_s / args.steps
     merge_cost = int(M.item())
 
@@ -284,7 +314,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int64" if kb == 8 else "int32",
+        "dtype": {"int32": "int32", "int64": "int64", "uint64": "u64", "float32": "f32"}[str(wl.keys.dtype)],
         "data": "synthetic",
         "config": {"workload": wl.name if args.method == "powersort" else f"{wl.name}_peeksort", "n": n,
                    "method": args.method, "key": str(wl.keys.dtype), "payload": "uint32 index",
@@ -295,6 +325,7 @@ def main() -> int:
         "kernel_groups": groups,
         "event_ms_per_step": round(ev_s / args.steps * 1e3, 4),
         "ms_per_step_without_events": round(plain_s / args.steps * 1e3, 4),
+        "per_sort_ms": percentiles_ms(per_sort_s),
         "gen_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:

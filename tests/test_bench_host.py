@@ -1,0 +1,51 @@
+"""Host-side logic of bench.py: the gate on the committed merge-pass counter
+figure, the per-sort percentiles, and the refusal of more than one GPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def committed_fields():
+    fields = {}
+    for line in open(bench.COUNTERS_MD).read().splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    return fields
+
+
+def test_traffic_gate_matches_only_what_was_measured():
+    f = committed_fields()
+    wl, launches, tile = f["workload"], int(f["merge_launches_per_sort"]), int(f["merge_tile"])
+    # the summary was taken on the current kernel source
+    assert f["kernel_source_digest"] == bench.merge_kernel_digest()
+    got = bench.measured_traffic(wl, launches, tile)
+    assert got == int(f["hbm_bytes_per_launch"])
+    # no more than a few percent above the algorithmic bytes it states
+    alg = int(f["algorithmic bytes per launch"].split()[0])
+    assert alg <= got < 1.05 * alg
+    assert bench.measured_traffic(wl + "_other", launches, tile) is None
+    assert bench.measured_traffic(wl, launches + 1, tile) is None
+    assert bench.measured_traffic(wl, launches, 4096 if tile != 4096 else 2048) is None
+
+
+def test_percentiles_ms():
+    p = bench.percentiles_ms([0.001 * i for i in range(1, 11)])  # 1..10 ms
+    assert p["sorts"] == 10
+    assert p["median"] == 5.5
+    assert abs(p["p10"] - 1.9) < 1e-9 and abs(p["p90"] - 9.1) < 1e-9
+    assert bench.percentiles_ms(np.array([0.002]))["median"] == 2.0
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
