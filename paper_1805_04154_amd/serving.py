@@ -8,9 +8,12 @@ open-loop with device-resident input buffers.  The server
   * keeps ``slots`` batches in flight at once, each on its own HIP stream with
     its own arena and workspace, so batches overlap on the device;
   * whenever a slot is free, forms a batch from the pending requests of the
-    oldest request's key type (in arrival order, as many as fit the arena),
-    gathers them into the arena, sorts them with one ps_segmented_sort (every
-    request an independent powersort) and scatters the results back;
+    oldest request's key type (in arrival order, as many as fit the slot) and
+    sorts them with one ps_segmented_sort, every request an independent
+    powersort.  Requests whose buffers come from a ``RequestPool`` lie back to
+    back in it in arrival order, so a batch of consecutive ones is a single
+    slice of the pool and is sorted there, in place.  Other requests are
+    gathered into the slot's arena and the results scattered back;
   * detects completions with events and records per-request latency from
     arrival to completion.
 
@@ -44,6 +47,8 @@ class ServedRequest:
     launch_s: float | None = None  # when its sort was enqueued
     done_s: float | None = None
     merge_cost: int | None = None
+    pool: "RequestPool | None" = None  # the pool its buffers are slices of
+    offset: int = 0                     # their first element in that pool
 
     @property
     def n(self) -> int:
@@ -52,6 +57,35 @@ class ServedRequest:
     @property
     def bytes(self) -> int:
         return self.n * (KEY_BYTES[self.keys.dtype] + 4)
+
+
+class RequestPool:
+    """Device storage for the requests of one key type: keys and a uint32
+    payload, handed out back to back in the order requests are made.  The
+    caller fills a request's buffers before submitting it; the server sorts
+    runs of consecutive requests in place as one segmented sort."""
+
+    def __init__(self, dtype: torch.dtype, capacity: int, device="cuda"):
+        if dtype not in KEY_BYTES:
+            raise ValueError(f"unsupported key type {dtype}")
+        self.dtype = dtype
+        self.capacity = int(capacity)
+        self.keys = torch.empty(self.capacity, dtype=dtype, device=device)
+        self.payload = torch.empty(self.capacity, dtype=torch.int32, device=device).view(torch.uint32)
+        self.used = 0
+
+    def request(self, rid: int, arrival_s: float, n: int) -> ServedRequest:
+        """A request of n keys whose buffers are the pool's next n elements."""
+        if self.used + n > self.capacity:
+            raise ValueError(f"pool of {self.capacity} keys has {self.capacity - self.used} left, asked for {n}")
+        a = self.used
+        self.used += n
+        return ServedRequest(rid, arrival_s, self.keys[a:a + n], self.payload[a:a + n], pool=self, offset=a)
+
+    def reset(self):
+        """Start handing out from the front again (earlier requests' buffers
+        are reused, so they must be finished with)."""
+        self.used = 0
 
 
 @dataclass
@@ -97,6 +131,19 @@ class SortServer:
 
     # ------------------------------------------------------------------ batches
 
+    @staticmethod
+    def _in_place(batch: list[ServedRequest]) -> bool:
+        """True if the batch is consecutive requests of one pool."""
+        pool = batch[0].pool
+        if pool is None:
+            return False
+        end = batch[0].offset
+        for r in batch:
+            if r.pool is not pool or r.offset != end:
+                return False
+            end += r.n
+        return True
+
     def _launch(self, slot: _Slot, batch: list[ServedRequest], now: float):
         dt = batch[0].keys.dtype
         kb = KEY_BYTES[dt]
@@ -104,14 +151,20 @@ class SortServer:
         offs = np.zeros(len(batch) + 1, np.int64)
         offs[1:] = np.cumsum(sizes)
         total = int(offs[-1])
-        keys = slot.arena_keys[: total * kb].view(dt)
-        pay = slot.arena_pay[:total]
+        in_place = self._in_place(batch)
+        if in_place:
+            a0 = batch[0].offset
+            keys, pay = batch[0].pool.keys[a0:a0 + total], batch[0].pool.payload[a0:a0 + total]
+        else:
+            keys = slot.arena_keys[: total * kb].view(dt)
+            pay = slot.arena_pay[:total]
         main = torch.cuda.current_stream()
         slot.stream.wait_stream(main)  # request buffers were produced on the caller's stream
         with torch.cuda.stream(slot.stream):
-            for r, a, b in zip(batch, offs[:-1], offs[1:]):
-                keys[a:b].copy_(r.keys)
-                pay[a:b].copy_(r.payload)
+            if not in_place:
+                for r, a, b in zip(batch, offs[:-1], offs[1:]):
+                    keys[a:b].copy_(r.keys)
+                    pay[a:b].copy_(r.payload)
             # pinned + non-blocking: the host does not wait for queued work
             off_h = torch.from_numpy(offs).pin_memory()
             off_t = off_h.to(keys.device, non_blocking=True)
@@ -119,9 +172,10 @@ class SortServer:
             costs = torch.zeros(len(batch), dtype=torch.int64, device=keys.device)
             binding.segmented_sort(keys, pay, off_t, min_run=self.min_run, merge_costs=costs,
                                    stream=slot.stream, workspace=slot.workspace)
-            for r, a, b in zip(batch, offs[:-1], offs[1:]):
-                r.keys.copy_(keys[a:b])
-                r.payload.copy_(pay[a:b])
+            if not in_place:
+                for r, a, b in zip(batch, offs[:-1], offs[1:]):
+                    r.keys.copy_(keys[a:b])
+                    r.payload.copy_(pay[a:b])
             ev = torch.cuda.Event()
             ev.record(slot.stream)
         slot.batch, slot.event, slot.costs, slot.start_s = batch, ev, costs, now
@@ -173,6 +227,10 @@ class SortServer:
                 rest = []
                 for r in pending:
                     fits_slot = r.keys.dtype == dt and keys + r.n <= s.capacity and len(batch) < self.max_segments
+                    if fits_slot and batch and batch[0].pool is not None:
+                        # a pool batch stays one slice: only the next request of that pool joins it
+                        last = batch[-1]
+                        fits_slot = r.pool is last.pool and r.offset == last.offset + last.n
                     need = BYTES_PER_KEY * r.n  # as in the slot sizing
                     if fits_slot and self.in_use + held + need <= self.budget:
                         batch.append(r)

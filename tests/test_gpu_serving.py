@@ -17,6 +17,24 @@ def make_requests(metas, keys, torch):
     return reqs
 
 
+def make_pool_requests(metas, keys, torch):
+    """The same requests with buffers from one RequestPool per key type."""
+    from paper_1805_04154_amd import serving
+    need = {}
+    for k in keys:
+        dt = torch.from_numpy(k[:0]).dtype
+        need[dt] = need.get(dt, 0) + len(k)
+    pools = {dt: serving.RequestPool(dt, n) for dt, n in need.items()}
+    reqs = []
+    for i, (m, k) in enumerate(zip(metas, keys)):
+        r = pools[torch.from_numpy(k[:0]).dtype].request(i, m.arrival_s, m.n)
+        r.keys.copy_(torch.from_numpy(k))
+        r.payload.copy_(torch.from_numpy(W.payload_for(m.n).view(np.int32)).view(torch.uint32))
+        reqs.append(r)
+    torch.cuda.synchronize()
+    return reqs
+
+
 def host(t, dtype):
     import torch
     if t.dtype == torch.uint32:
@@ -104,3 +122,34 @@ def test_oversized_request_is_rejected(trace):
     srv = serving.SortServer(hbm_budget_bytes=serving.BYTES_PER_KEY * (metas[big].n // 2), slots=1)
     with pytest.raises(ValueError):
         srv.serve(reqs, realtime=False)
+
+
+def test_pool_requests_sorted_in_place(trace):
+    # requests from pools are batched as slices of them and sorted there;
+    # under a tight budget the batches break at different places
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    biggest = max(m.n for m in metas)
+    for budget, slots in ((1 << 30, 2), (2 * serving.BYTES_PER_KEY * biggest + (1 << 20), 2), (1 << 30, 1)):
+        reqs = make_pool_requests(metas, keys, torch)
+        done = serving.SortServer(hbm_budget_bytes=budget, slots=slots).serve(reqs, realtime=False)
+        torch.cuda.synchronize()
+        check(done, refs, keys)
+    reqs = make_pool_requests(metas, keys, torch)
+    done = serving.serve_plain(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+
+
+def test_pool_and_plain_requests_mixed(trace):
+    # every third request has buffers of its own: pool batches stop at it
+    import torch
+    from paper_1805_04154_amd import serving
+    metas, keys, refs = trace
+    pooled = make_pool_requests(metas, keys, torch)
+    own = make_requests(metas, keys, torch)
+    reqs = [own[i] if i % 3 == 0 else pooled[i] for i in range(len(metas))]
+    done = serving.SortServer(hbm_budget_bytes=1 << 30, slots=2).serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)

@@ -42,6 +42,29 @@ def test_request_trace_shape():
     assert 60 <= len(metas) <= 140
 
 
+def test_request_pool_and_in_place_batches():
+    # buffers are handed out back to back; a batch is sorted in place only
+    # when it is consecutive requests of one pool
+    import torch
+    from paper_1805_04154_amd.serving import RequestPool, ServedRequest, SortServer
+    pool = RequestPool(torch.int32, 100, device="cpu")
+    a, b, c = pool.request(0, 0.0, 30), pool.request(1, 0.0, 50), pool.request(2, 0.0, 20)
+    assert (a.offset, b.offset, c.offset) == (0, 30, 80) and pool.used == 100
+    b.keys.fill_(7)
+    assert int(pool.keys[30:80].sum()) == 7 * 50  # views of the pool's storage
+    with pytest.raises(ValueError):
+        pool.request(3, 0.0, 1)
+    assert SortServer._in_place([a, b, c]) and SortServer._in_place([b]) and SortServer._in_place([b, c])
+    assert not SortServer._in_place([a, c])  # a gap
+    assert not SortServer._in_place([b, a])  # out of order
+    other = RequestPool(torch.int32, 10, device="cpu").request(0, 0.0, 10)
+    assert not SortServer._in_place([c, other])
+    own = ServedRequest(9, 0.0, torch.zeros(5, dtype=torch.int32), torch.zeros(5, dtype=torch.int32))
+    assert not SortServer._in_place([own]) and not SortServer._in_place([a, own])
+    pool.reset()
+    assert pool.request(4, 0.0, 100).offset == 0
+
+
 def test_busy_time_is_the_union_of_intervals():
     from paper_1805_04154_amd.serving import busy_time
     assert busy_time([]) == 0.0
