@@ -29,7 +29,7 @@
  *   - Keys: int32, uint32, int64, uint64 in their natural order; float32 in
  *     IEEE-754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN;
  *     NaNs ordered by payload bits).  Output keys keep their bit patterns.
- *   - Limits: n_total < 2^32 elements per call, every segment < 2^31.
+ *   - Limits: n_total < 2^31 elements per call (so every segment < 2^31).
  *   - No exceptions or aborts cross this ABI.
  */
 #ifndef POWERSORT_HIP_H
@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
     PS_OK = 0,
     PS_ERR_INVALID_ARG = -1,   /* null pointer, bad key type, bad segment offsets, ... */
-    PS_ERR_TOO_LARGE = -2,     /* a segment >= 2^31 or n_total >= 2^32 */
+    PS_ERR_TOO_LARGE = -2,     /* n or n_total >= 2^31 */
     PS_ERR_OUT_OF_MEMORY = -3, /* scratch allocation failed (nothing enqueued) */
     PS_ERR_HIP = -4,           /* a HIP runtime call failed; see ps_last_error() */
     PS_ERR_UNSUPPORTED = -5    /* option outside the supported range (e.g. min_run > 64) */

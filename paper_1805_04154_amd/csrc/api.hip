@@ -666,7 +666,7 @@ static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     c.w = o.w;
     c.peek = o.peek;
     c.nbuf = o.nbuf;
-    if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^32");
+    if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^31");
     if (c.nseg == 0) return fail(PS_ERR_INVALID_ARG, "num_segments must be at least 1");
     if (c.nseg >= kMaxTotal) return fail(PS_ERR_TOO_LARGE, "too many segments");
     if (!c.d_offsets && c.nseg != 1) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");

@@ -119,7 +119,9 @@ constexpr int kMaxPass = 64;
 
 // Per-call limits.
 constexpr uint64_t kMaxSegment = (1ull << 31) - 1;
-constexpr uint64_t kMaxTotal = 0xFFFFFFFFull;
+// Positions are u32 in every kernel: below 2^31, a position plus any
+// grid stride or tile length stays below 2^32, so no index can wrap.
+constexpr uint64_t kMaxTotal = (1ull << 31) - 1;
 constexpr uint64_t kMaxTreeLeaves = 1ull << 28;  // leaves of ps_alphabetic_tree
 
 __device__ __forceinline__ int clz32(uint32_t x) { return __clz(x); }

@@ -52,6 +52,12 @@ def test_argument_validation_without_launch(lib):
     assert lib.ps_segmented_sort(fake, None, None, 3, 10, 0, None, None, None, None) == -1
     assert lib.ps_segmented_sort(fake, None, fake, 0, 10, 0, None, None, None, None) == -1
     assert lib.ps_segmented_sort(fake, None, fake, 2, 1 << 32, 0, None, None, None, None) == -2
+    # u32 positions: n_total itself must stay below 2^31
+    assert lib.ps_segmented_sort(fake, None, fake, 2, 1 << 31, 0, None, None, None, None) == -2
+    assert b"2^31" in lib.ps_last_error()
+    assert lib.ps_segmented_merge_cost(fake, fake, 2, 1 << 31, 0, None, fake, None, None) == -2
+    assert lib.ps_workspace_bytes(1 << 31, 2, 0, 1, None) == 0
+    assert lib.ps_workspace_bytes((1 << 31) - 1, 2, 0, 1, None) > 0
     assert lib.ps_merge_cost(fake, 10, 0, None, None, None) == -1
     assert lib.ps_segmented_merge_cost(fake, fake, 2, 10, 0, None, None, None, None) == -1
     assert lib.ps_inspect(fake, None, 1, 10, 0, None, None, None) == -1
