@@ -126,6 +126,88 @@ def cpu_baseline(wl, budget_s: float, method: str = "powersort") -> dict:
                       f"{dt:.2f} s"}
 
 
+def host_cores() -> int:
+    """Cores this process may run on, at most 16 (one GPU's share of a box)."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def batched_cpu_baseline(wl, budget_s: float) -> dict:
+    """The oracle on the batch's segments, each an independent powersort: one
+    core in segment order for budget_s / 2, then every usable core (one
+    thread each; the C oracle runs without the GIL) on the following segments
+    for as long.  Segment sizes are i.i.d., so either prefix is a fair sample."""
+    import threading
+    import oracle
+    offs = wl.offsets.astype(np.int64)
+    nseg = offs.shape[0] - 1
+
+    def one(i):
+        a, b = int(offs[i]), int(offs[i + 1])
+        oracle.powersort(wl.keys[a:b], wl.payload[a:b], details=False)
+        return b - a
+
+    t0 = time.perf_counter()
+    k1, i = 0, 0
+    while i < nseg and time.perf_counter() - t0 < budget_s / 2:
+        k1 += one(i)
+        i += 1
+    dt1 = time.perf_counter() - t0
+    first_all = i
+    cores = host_cores()
+    lock = threading.Lock()
+    state = {"next": i, "keys": 0}
+    t0 = time.perf_counter()
+
+    def worker():
+        while True:
+            with lock:
+                if state["next"] >= nseg or time.perf_counter() - t0 >= budget_s / 2:
+                    return
+                j = state["next"]
+                state["next"] += 1
+            kk = one(j)
+            with lock:
+                state["keys"] += kk
+
+    threads = [threading.Thread(target=worker) for _ in range(cores)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    dt_all = time.perf_counter() - t0
+    return {"value": round(k1 / dt1, 1), "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"segments 0..{first_all - 1} of {nseg} ({k1} keys), one oracle powersort per segment, "
+                      f"single thread on the host CPU ({host_cpu()}), {dt1:.2f} s",
+            "all_cores": {"value": round(state["keys"] / dt_all, 1), "unit": "keys/s", "cores": cores,
+                          "sample": f"segments {first_all}..{state['next'] - 1} ({state['keys']} keys), "
+                                    f"{cores} threads each running oracle calls on whole segments, {dt_all:.2f} s"}}
+
+
+def served_cpu_baseline(keys_list, budget_s: float) -> dict:
+    """Single-core oracle service time per request, over the trace's first
+    requests until budget_s: p50/p99 of one oracle powersort call each."""
+    import oracle
+    from paper_1805_04154_amd import workloads as W
+    ts, nk = [], 0
+    t0 = time.perf_counter()
+    for k in keys_list:
+        if time.perf_counter() - t0 >= budget_s:
+            break
+        pay = W.payload_for(len(k))
+        t = time.perf_counter()
+        oracle.powersort(k, pay, details=False)
+        ts.append(time.perf_counter() - t)
+        nk += len(k)
+    a = np.asarray(ts) * 1e3
+    return {"value": round(float(nk / (a.sum() / 1e3)), 1), "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "service_ms": {"p50": round(float(np.percentile(a, 50)), 3), "p99": round(float(np.percentile(a, 99)), 3)},
+            "sample": f"first {len(ts)} requests of the trace ({nk} keys), one oracle powersort call each, "
+                      f"single thread on the host CPU ({host_cpu()})"}
+
+
 def host_cpu() -> str:
     """The host CPU's model name, from /proc/cpuinfo."""
     try:
@@ -451,6 +533,8 @@ def run_batched(args) -> int:
         "kernel_groups_ms": groups,
         "gen_s": round(t_gen, 1),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batched_cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -533,6 +617,8 @@ def run_served(args) -> int:
         "saturated_speedup_vs_plain": round(sat["keys_per_s"] / out_runs["plain_saturated"]["keys_per_s"], 2),
         "gen_s": round(t_gen, 1),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = served_cpu_baseline(keys, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -63,10 +63,11 @@ static int f32_total_less(uint32_t a, uint32_t b) {
     return a > b;                 /* both negative: larger magnitude, smaller value */
 }
 
-/* Key comparisons made by the last oracle_powersort / oracle_peeksort call
- * (Thm. "powersort" / "peeksort" bound them); every comparison goes through
- * key_less.  The oracle is single-threaded. */
-static uint64_t g_comparisons;
+/* Key comparisons made by the calling thread's last oracle_powersort /
+ * oracle_peeksort call (Thm. "powersort" / "peeksort" bound them); every
+ * comparison goes through key_less.  Each call runs on one thread; the count
+ * is per thread so that independent calls may run on several threads. */
+static _Thread_local uint64_t g_comparisons;
 
 /* key_less(x, y): the key stored at x orders strictly before the key at y. */
 static int key_less(const arr_t *A, const unsigned char *x, const unsigned char *y) {

@@ -51,3 +51,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_batched_and_served_oracle_baselines():
+    # bounded samples: whole segments (requests) in order, never past the input
+    from paper_1805_04154_amd import workloads as W
+    wl = W.batched_random_runs(nseg=8)
+    r = bench.batched_cpu_baseline(wl, 1.0)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
+    assert 1 <= r["all_cores"]["cores"] <= 16 and r["all_cores"]["value"] > 0
+    metas = W.trace_meta(rate_hz=2000, duration_s=0.01, lo_exp=8, hi_exp=12, seed_index=11)
+    keys = W.materialize(metas, workers=1)
+    s = bench.served_cpu_baseline(keys, 1.0)
+    assert s["service_ms"]["p50"] <= s["service_ms"]["p99"] and s["value"] > 0
