@@ -340,8 +340,11 @@ static hipEvent_t prof_event() {
         g_prof.pool.pop_back();
         return e;
     }
+    // Timing only: no system-scope fence when the event is recorded (that
+    // fence writes back and invalidates caches, which slows the work after
+    // it).  Results reach the caller through the stream's own completion.
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
