@@ -208,6 +208,16 @@ def _segment_keys(args):
     return 0
 
 
+def batched_offsets(nseg: int = 4096, lo_exp: int = 10, hi_exp: int = 22, seed_index: int = 3) -> np.ndarray:
+    """Segment offsets of ``batched_random_runs`` (sizes log-uniform in
+    [2^lo_exp, 2^hi_exp]) without generating the keys."""
+    rng = config_rng(seed_index)
+    sizes = np.floor(np.exp(rng.uniform(lo_exp * math.log(2), hi_exp * math.log(2), size=nseg))).astype(np.int64)
+    offsets = np.zeros(nseg + 1, np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    return offsets
+
+
 def batched_random_runs(nseg: int = 4096, lo_exp: int = 10, hi_exp: int = 22, desc_frac: float = 0.25,
                         seed_index: int = 3, key_dtype=np.int32, workers: int | None = None) -> Workload:
     """``nseg`` arrays with sizes log-uniform in [2^lo_exp, 2^hi_exp], each a
@@ -215,10 +225,7 @@ def batched_random_runs(nseg: int = 4096, lo_exp: int = 10, hi_exp: int = 22, de
 
     Segment g draws from its own generator (spawned from the workload seed),
     so the result does not depend on the number of worker processes."""
-    rng = config_rng(seed_index)
-    sizes = np.floor(np.exp(rng.uniform(lo_exp * math.log(2), hi_exp * math.log(2), size=nseg))).astype(np.int64)
-    offsets = np.zeros(nseg + 1, np.uint64)
-    offsets[1:] = np.cumsum(sizes)
+    offsets = batched_offsets(nseg, lo_exp, hi_exp, seed_index)
     total = int(offsets[-1])
     seqs = np.random.SeedSequence(BASE_SEED + 100 + seed_index).spawn(nseg)
     dt = np.dtype(key_dtype)
