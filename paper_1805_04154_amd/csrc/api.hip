@@ -590,8 +590,17 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         // node of a segment of at most N keys has a power above pbound.
         uint32_t pbound = 1;
         while (((uint64_t)1 << pbound) * (c.w + 1) < 2 * c.N) ++pbound;
+        // Only nodes of more than kFuse elements merge in a pass (smaller ones
+        // merge inside fused subtrees).  Every internal boundary of a node of
+        // power p has power >= p, so its leaf midpoints share one cell of
+        // width 2^(1-p) and each of its leaves is shorter than n 2^(2-p): the
+        // node holds fewer than 3n / 2^(p-1) elements.  Passes with
+        // kFuse 2^(p-1) >= 3N therefore hold no node.
+        uint32_t pfuse = 1;
+        while (((uint64_t)kFuse << pfuse) < 3 * c.N) ++pfuse;
         const uint32_t pmax = c.peek ? std::min<uint32_t>(kMaxPass, peek_levels)
-                                     : std::min<uint32_t>(std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1), pbound);
+                                     : std::min<uint32_t>(std::min<uint32_t>(kMaxPower, ilog2_floor(c.N) + 1),
+                                                          std::min(pbound, pfuse));
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
         auto stage = [&](int group, int s, uint32_t p, uint32_t grid) {

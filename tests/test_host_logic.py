@@ -100,6 +100,42 @@ def pass_bound(n: int, w: int) -> int:
     return min(b, max(n, 1).bit_length())
 
 
+def fused_pass_bound(n: int, fuse: int = 4096) -> int:
+    """Largest power of a node of more than ``fuse`` elements: its internal
+    boundaries have powers >= p, so its leaf midpoints share one cell of
+    width 2^(1-p) and each leaf is shorter than n 2^(2-p); its size is below
+    3n / 2^(p-1).  The smallest p with fuse 2^p >= 3n."""
+    p = 1
+    while (fuse << p) < 3 * n:
+        p += 1
+    return p
+
+
+@pytest.mark.parametrize("w", [1, 24, 64])
+def test_nodes_above_the_fused_size_are_within_the_fused_pass_bound(w):
+    # merge passes above this bound would hold only nodes of at most 4096
+    # elements, which merge inside fused subtrees, so the library skips them
+    import math
+    import oracle
+    rng = W.make_rng(78)
+    worst = 0
+    for n in (5000, 9000, 50001, 300000, 1 << 20):
+        inputs = [W.random_permutation(rng, n), rng.integers(0, 5, size=n),
+                  W.random_runs(rng, n, max(2.0, math.sqrt(n)), 0.25), W.random_runs(rng, n, 40.0, 0.25),
+                  W.random_runs(rng, n, 3000.0, 0.1)]
+        for v in inputs:
+            ref = oracle.powersort(np.asarray(v).astype(np.int32), None, min_run=w)
+            starts = ref.starts.astype(np.int64)
+            at = {int(s): j for j, s in enumerate(starts)}
+            for lo, mid, hi in ref.merges.astype(np.int64):
+                if hi - lo > 4096:
+                    pw = int(ref.powers[at[int(mid)] - 1])
+                    assert pw <= fused_pass_bound(n), (n, w, lo, mid, hi, pw)
+                    worst = max(worst, fused_pass_bound(n) - pw)
+    assert worst >= 0
+    assert fused_pass_bound(1 << 28) == 18 and fused_pass_bound(3 << 10) == 2
+
+
 @pytest.mark.parametrize("w", [1, 2, 3, 7, 24, 64])
 def test_every_node_power_is_within_the_pass_bound(w):
     # the library runs merge passes pmax..1 only; a node above the bound
