@@ -29,7 +29,9 @@
  *   - Keys: int32, uint32, int64, uint64 in their natural order; float32 in
  *     IEEE-754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN;
  *     NaNs ordered by payload bits).  Output keys keep their bit patterns.
- *   - Limits: n_total < 2^31 elements per call (so every segment < 2^31).
+ *   - Limits: every segment (and every ps_sort, ps_merge_cost and
+ *     ps_inspect input) holds fewer than 2^31 elements; a segmented batch
+ *     may hold up to 2^63 - 1 elements in all (uint64 offsets).
  *   - No exceptions or aborts cross this ABI.
  */
 #ifndef POWERSORT_HIP_H
@@ -45,7 +47,8 @@ extern "C" {
 typedef enum {
     PS_OK = 0,
     PS_ERR_INVALID_ARG = -1,   /* null pointer, bad key type, bad segment offsets, ... */
-    PS_ERR_TOO_LARGE = -2,     /* n or n_total >= 2^31 */
+    PS_ERR_TOO_LARGE = -2,     /* a segment of 2^31 or more elements, n_total >= 2^63, or a
+                                  sort too large for the fixed scratch of ps_sort_no_alloc */
     PS_ERR_OUT_OF_MEMORY = -3, /* scratch allocation failed (nothing enqueued) */
     PS_ERR_HIP = -4,           /* a HIP runtime call failed; see ps_last_error() */
     PS_ERR_UNSUPPORTED = -5    /* option outside the supported range (e.g. min_run > 64) */
@@ -95,8 +98,10 @@ typedef struct {
 /* Bytes of device scratch one call needs for n_total elements in
  * num_segments segments (ps_sort: num_segments = 1).  has_payload is 0 or 1.
  * About 2 n_total (key bytes + 4 if has_payload) plus metadata, or half the
- * data part with PS_FLAG_COMPACT_SCRATCH in opt->flags.  Returns 0 for
- * invalid arguments. */
+ * data part with PS_FLAG_COMPACT_SCRATCH in opt->flags.  A batch above
+ * 2^31 - 1 elements runs in chunks of at most 2^31 - 1 (see
+ * ps_segmented_sort), so its figure is that of 2^31 - 1 elements.  Returns 0
+ * for invalid arguments. */
 size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
                           const ps_options *opt);
 
@@ -112,11 +117,19 @@ ps_status ps_sort(void *keys, uint32_t *payload, uint64_t n, ps_key_type key_typ
  * powersort with its own n and origin (the paper's nodePower takes the
  * subarray bounds, App. B.4), all segments in one batch of launches.
  * d_offsets: num_segments + 1 uint64 on the device, non-decreasing, with
- * d_offsets[0] = 0 and d_offsets[num_segments] = n_total.  Empty segments are
- * allowed.  d_merge_costs (nullable): num_segments uint64, M per segment.
- * d_status (nullable, 1 x int32): receives PS_OK, or PS_ERR_INVALID_ARG /
- * PS_ERR_TOO_LARGE when the offsets fail validation on the device; in that
- * case the keys are left in an unspecified order (no out-of-bounds access). */
+ * d_offsets[0] = 0 and d_offsets[num_segments] = n_total; every segment
+ * below 2^31 elements.  Empty segments are allowed.  d_merge_costs
+ * (nullable): num_segments uint64, M per segment.  d_status (nullable,
+ * 1 x int32): receives PS_OK, or PS_ERR_INVALID_ARG / PS_ERR_TOO_LARGE when
+ * the offsets fail validation on the device; in that case the keys are left
+ * in an unspecified order (no out-of-bounds access).
+ * Batches of n_total >= 2^31 (up to 2^63 - 1): the library reads the offsets
+ * back to the host once (this synchronises `stream`, so such a call cannot
+ * be captured into a graph), validates them there (invalid offsets: the
+ * error status is returned, nothing further is enqueued) and sorts the batch
+ * as consecutive chunks of whole segments, each below 2^31 elements, one
+ * after another on `stream` in one workspace.  Results are those of one
+ * call. */
 ps_status ps_segmented_sort(void *keys, uint32_t *payload, const uint64_t *d_offsets, uint64_t num_segments,
                             uint64_t n_total, ps_key_type key_type, const ps_options *opt,
                             uint64_t *d_merge_costs, int32_t *d_status, void *stream);
@@ -128,7 +141,8 @@ ps_status ps_merge_cost(const void *keys, uint64_t n, ps_key_type key_type, cons
                         uint64_t *d_merge_cost, void *stream);
 
 /* Per-segment merge costs of ps_segmented_sort without sorting.
- * d_merge_costs: num_segments uint64.  d_status as in ps_segmented_sort. */
+ * d_merge_costs: num_segments uint64.  d_status, and batches of 2^31 or
+ * more elements, as in ps_segmented_sort. */
 ps_status ps_segmented_merge_cost(const void *keys, const uint64_t *d_offsets, uint64_t num_segments,
                                   uint64_t n_total, ps_key_type key_type, const ps_options *opt,
                                   uint64_t *d_merge_costs, int32_t *d_status, void *stream);
@@ -148,7 +162,7 @@ typedef struct {
 
 /* Runs the non-moving part of the method (partition, powers, tree) on keys
  * and copies its intermediate arrays into `out` (each member nullable).
- * d_offsets may be NULL for one segment [0, n_total). */
+ * d_offsets may be NULL for one segment [0, n_total).  n_total < 2^31. */
 ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_segments, uint64_t n_total,
                      ps_key_type key_type, const ps_options *opt, ps_inspect_out *out, void *stream);
 
@@ -171,6 +185,26 @@ ps_status ps_inspect(const void *keys, const uint64_t *d_offsets, uint64_t num_s
 ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uint8_t *d_powers,
                              uint32_t *d_node_left, uint32_t *d_node_right, uint8_t *d_leaf_depth, uint64_t *d_cost,
                              int32_t *d_status, void *stream);
+
+/* ps_sort for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * allocation): the same sort, merge cost and arguments as ps_sort, with
+ * scratch taken from a fixed array of 128 MiB that the library keeps on
+ * every device it runs on (until the process ends) instead of the per-stream
+ * pool.  It calls no hipMalloc, hipFree or other allocating routine; the
+ * first call on a device looks up the array's address there.  The caller
+ * still owns keys, payload and d_merge_cost.  opt->workspace must be NULL
+ * (PS_ERR_INVALID_ARG otherwise).  A sort whose ps_workspace_bytes(n, 1,
+ * key_type, payload != NULL, opt) exceeds 128 MiB returns PS_ERR_TOO_LARGE
+ * with nothing enqueued; at the default minimum run that is above 6 750 752
+ * 4-byte keys with a payload (11 292 832 without) or 4 813 775 8-byte keys
+ * with a payload (6 750 768 without).  All calls on one device share that device's
+ * array, and each call rewrites what it needs: calls that overlap on one
+ * device (on different streams or from different threads) race and give
+ * undefined results, so the caller serialises them, e.g. on one stream.
+ * Profiling (ps_profile_enable) does not time these calls. */
+ps_status ps_sort_no_alloc(void *keys, uint32_t *payload, uint64_t n, ps_key_type key_type, const ps_options *opt,
+                           uint64_t *d_merge_cost, void *stream);
 
 /* Launch shape of the data-movement kernels (process-wide).  Every value
  * changes only speed, never results: grids are workgroup counts of

@@ -24,6 +24,11 @@ Parity status per function (pins live in the tests' oracle-pin suite):
                        nearest-boundary formulation of the split rule
   segmented_peeksort   pinned through peeksort (one call per segment)
   peek_merge_order     pinned: Fig. 1 left tree, Thm. "peeksort" bound
+  topdown_mergesort    pinned: stable-sort output, M = 0 on sorted input, the
+  bottomup_mergesort   closed forms of the non-adaptive recursions on strictly
+                       decreasing input (no merge check fires), and M
+                       recomputed from the original data over the fixed
+                       recursion shapes
   Result.comparisons   pinned: exact counts on sorted / reversed / two-run
                        inputs, n - 1 for run detection plus at most size - 1
                        per merge, and the comparison bounds of Thm.
@@ -91,6 +96,10 @@ def _load():
                                                 ctypes.c_void_p, u64p]
         lib.oracle_last_comparisons.restype = ctypes.c_uint64
         lib.oracle_last_comparisons.argtypes = []
+        for name in ("oracle_topdown_mergesort", "oracle_bottomup_mergesort"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, u64p]
         lib.oracle_segmented_peeksort.restype = ctypes.c_int
         lib.oracle_segmented_peeksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
@@ -251,3 +260,29 @@ def peek_merge_order(lengths) -> tuple[np.ndarray, np.ndarray, int]:
     if _load().oracle_peek_merge_order(_ptr(L), r, _ptr(merges), _ptr(depth), ctypes.byref(M)) != 0:
         raise ValueError("run lengths must be positive")
     return merges[: max(r - 1, 0)].copy(), depth[:r].copy(), M.value
+
+
+def _elementary(name: str, keys: np.ndarray, payload: np.ndarray | None, min_run: int) -> Result:
+    lib = _load()
+    kt = key_type_of(keys)
+    k = np.ascontiguousarray(keys).copy()
+    p = None if payload is None else np.ascontiguousarray(payload, dtype=np.uint32).copy()
+    M = ctypes.c_uint64(0)
+    if getattr(lib, name)(_ptr(k), _ptr(p), k.shape[0], KEY_TYPES[kt], min_run, ctypes.byref(M)) != 0:
+        raise RuntimeError(f"{name} failed")
+    return Result(k, p, None, None, None, M.value, comparisons=int(lib.oracle_last_comparisons()))
+
+
+def topdown_mergesort(keys: np.ndarray, payload: np.ndarray | None = None,
+                      min_run: int = DEFAULT_MIN_RUN) -> Result:
+    """Top-down mergesort with the already-in-order check before each merge
+    and insertion sort below min_run elements (Sec. 4.1), on copies; the
+    Result holds keys, payload and merge_cost."""
+    return _elementary("oracle_topdown_mergesort", keys, payload, min_run)
+
+
+def bottomup_mergesort(keys: np.ndarray, payload: np.ndarray | None = None,
+                       min_run: int = DEFAULT_MIN_RUN) -> Result:
+    """Bottom-up mergesort from insertion-sorted chunks of min_run elements,
+    with the already-in-order check before each merge (Sec. 4.1), on copies."""
+    return _elementary("oracle_bottomup_mergesort", keys, payload, min_run)

@@ -480,8 +480,97 @@ int oracle_segmented_peeksort(void *keys, uint32_t *payload, const uint64_t *off
     return 0;
 }
 
-/* Key comparisons made by the most recent oracle_powersort or
- * oracle_peeksort call: run detection, min-run insertion sorts and merges. */
+/* ---------------------------------------------------- elementary mergesorts
+ *
+ * The two non-natural mergesorts the paper's experiments compare against
+ * (Sec. 4.1, setup): top-down and bottom-up mergesort in Sedgewick's form,
+ * each with two changes the paper states: before a merge, check whether its
+ * two runs are already in order (the left run's last key not above the right
+ * run's first key) and skip the merge if so; and sort small pieces by
+ * insertion sort: top-down, every subproblem of at most w elements;
+ * bottom-up, the chunks of w elements it starts from.  Both merge with
+ * merge_runs above (stable, left run first on ties).  The merge cost counts
+ * the result sizes of the merges actually run (Sec. 2.2); insertion sorts are
+ * not merges.
+ * Parity status: pinned (stable-sort output; M = 0 on sorted input; the
+ * closed forms of the non-adaptive recursions on strictly decreasing input,
+ * where no check fires; and M recomputed from the original data by the
+ * condition "some key of the right part is below some key of the left part"
+ * over the fixed recursion shapes).
+ */
+
+/* Top-down: A[lo..hi) splits as in Sedgewick's m = (l + r) / 2 on inclusive
+ * bounds, so the left half takes the ceiling of half the elements. */
+static void topdown_rec(arr_t *A, uint64_t lo, uint64_t hi, uint32_t w, unsigned char *tk, uint32_t *tp,
+                        uint64_t *M) {
+    if (hi - lo <= w) {
+        insertion_sort(A, lo, hi, 0);
+        return;
+    }
+    uint64_t mid = lo + (hi - lo + 1) / 2;
+    topdown_rec(A, lo, mid, w, tk, tp, M);
+    topdown_rec(A, mid, hi, w, tk, tp, M);
+    if (less_at(A, mid, mid - 1)) {  /* not already in order */
+        merge_runs(A, lo, mid, hi, tk, tp);
+        *M += hi - lo;
+    }
+}
+
+/* Sort keys[0..n) (payload alongside, may be NULL) by top-down mergesort
+ * with cutoff w; merge cost via merge_cost_out.  Returns 0 or -1. */
+int oracle_topdown_mergesort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
+                             uint64_t *merge_cost_out) {
+    if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
+    arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
+    g_comparisons = 0;
+    uint64_t M = 0;
+    if (n > 0) {
+        unsigned char *tk = (unsigned char *)malloc(n * A.ks);
+        uint32_t *tp = (uint32_t *)malloc(n * sizeof(uint32_t));
+        if (!tk || !tp) { free(tk); free(tp); return -1; }
+        topdown_rec(&A, 0, n, w, tk, tp, &M);
+        free(tk);
+        free(tp);
+    }
+    if (merge_cost_out) *merge_cost_out = M;
+    return 0;
+}
+
+/* Sort keys[0..n) by bottom-up mergesort: insertion-sort the chunks
+ * [k w, (k+1) w), then for run length m = w, 2w, 4w, ... merge each pair of
+ * neighbouring runs [i, i+m) and [i+m, min(i+2m, n)) for i = 0, 2m, 4m, ...
+ * while i + m < n (a last run without a partner stays as it is).  Returns 0
+ * or -1. */
+int oracle_bottomup_mergesort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
+                              uint64_t *merge_cost_out) {
+    if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
+    arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
+    g_comparisons = 0;
+    uint64_t M = 0;
+    if (n > 0) {
+        unsigned char *tk = (unsigned char *)malloc(n * A.ks);
+        uint32_t *tp = (uint32_t *)malloc(n * sizeof(uint32_t));
+        if (!tk || !tp) { free(tk); free(tp); return -1; }
+        for (uint64_t s = 0; s < n; s += w) insertion_sort(&A, s, (s + w < n) ? s + w : n, 0);
+        for (uint64_t m = w; m < n; m *= 2) {
+            for (uint64_t lo = 0; lo + m < n; lo += 2 * m) {
+                uint64_t mid = lo + m, hi = (lo + 2 * m < n) ? lo + 2 * m : n;
+                if (less_at(&A, mid, mid - 1)) {
+                    merge_runs(&A, lo, mid, hi, tk, tp);
+                    M += hi - lo;
+                }
+            }
+        }
+        free(tk);
+        free(tp);
+    }
+    if (merge_cost_out) *merge_cost_out = M;
+    return 0;
+}
+
+/* Key comparisons made by the most recent oracle_powersort,
+ * oracle_peeksort or elementary mergesort call on this thread: run
+ * detection, min-run insertion sorts and merges. */
 uint64_t oracle_last_comparisons(void) {
     return g_comparisons;
 }

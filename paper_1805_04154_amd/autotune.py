@@ -18,6 +18,10 @@ import torch
 from . import binding
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "powersort_hip", "tuning.json")
+# Shapes measured on an MI355X and shipped with the package: consulted after
+# the user's cache, so that a run without a tuning pass starts from a tuned
+# shape (written by tune() + save_cache(..., path=SHIPPED_CACHE)).
+SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
 def candidates(small: bool = False) -> list[dict]:
@@ -97,10 +101,21 @@ def save_cache(key: str, tuning: dict, ms: float, path: str = DEFAULT_CACHE):
     os.replace(tmp, path)
 
 
-def apply_cached(key: str, path: str = DEFAULT_CACHE) -> dict | None:
-    """Set the cached shape for a signature, if one exists."""
-    entry = load_cache(path).get(key)
-    if entry:
-        binding.set_tuning(entry["tuning"])
-        return entry["tuning"]
+def lookup(key: str, paths=(DEFAULT_CACHE, SHIPPED_CACHE)) -> dict | None:
+    """The cached shape for a signature: the first cache that holds it
+    (paths: one cache file or a sequence of them)."""
+    if isinstance(paths, (str, os.PathLike)):
+        paths = (paths,)
+    for path in paths:
+        entry = load_cache(path).get(key)
+        if entry:
+            return entry["tuning"]
     return None
+
+
+def apply_cached(key: str, paths=(DEFAULT_CACHE, SHIPPED_CACHE)) -> dict | None:
+    """Set the cached shape for a signature, if one exists."""
+    tuning = lookup(key, paths)
+    if tuning:
+        binding.set_tuning(tuning)
+    return tuning

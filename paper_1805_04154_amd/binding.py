@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "PS_OK", -1: "PS_ERR_INVALID_ARG", -2: "PS_ERR_TOO_LARGE", -3
 KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, torch.float32: 4}
 
 # Every symbol include/powersort_hip.h declares.
-EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_segmented_sort", "ps_merge_cost", "ps_segmented_merge_cost",
+EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_sort_no_alloc", "ps_segmented_sort", "ps_merge_cost",
+           "ps_segmented_merge_cost",
            "ps_inspect", "ps_alphabetic_tree", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable",
            "ps_profile_read", "ps_release",
            "ps_status_string", "ps_last_error")
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.ps_workspace_bytes.argtypes = [u64, u64, i32, i32, opt]
     lib.ps_sort.restype = i32
     lib.ps_sort.argtypes = [vp, vp, u64, i32, opt, vp, vp]
+    lib.ps_sort_no_alloc.restype = i32
+    lib.ps_sort_no_alloc.argtypes = [vp, vp, u64, i32, opt, vp, vp]
     lib.ps_segmented_sort.restype = i32
     lib.ps_segmented_sort.argtypes = [vp, vp, vp, u64, u64, i32, opt, vp, vp, vp]
     lib.ps_merge_cost.restype = i32
@@ -143,6 +146,32 @@ def _dev_check(*ts):
             raise ValueError("tensors must be contiguous")
 
 
+def _check_payload(keys: torch.Tensor, payload: torch.Tensor | None):
+    if payload is not None and (payload.dtype not in (torch.int32, torch.uint32) or payload.numel() != keys.numel()):
+        raise ValueError("payload must be a 32-bit tensor with one entry per key")
+
+
+def _check_words(t: torch.Tensor | None, name: str, dtypes: tuple, count: int):
+    """t (if given) must hold at least count elements of one of dtypes."""
+    if t is None:
+        return
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+    if t.numel() < count:
+        raise ValueError(f"{name} needs at least {count} elements, has {t.numel()}")
+
+
+_U64 = (torch.int64, torch.uint64)
+_I32 = (torch.int32,)
+
+
+def _check_offsets(offsets: torch.Tensor) -> int:
+    """Segment offsets: a 1-D 64-bit tensor of num_segments + 1 >= 2 entries; returns num_segments."""
+    if offsets.dtype not in _U64 or offsets.dim() != 1 or offsets.numel() < 2:
+        raise ValueError("offsets must be a 1-D int64 tensor of num_segments + 1 >= 2 entries")
+    return offsets.numel() - 1
+
+
 def _stream(stream) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
@@ -162,12 +191,28 @@ def sort(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int |
 
     merge_cost: optional 1-element int64 device tensor that receives M (as uint64 bits)."""
     lib = load_library()
+    _check_payload(keys, payload)
+    _check_words(merge_cost, "merge_cost", _U64, 1)
     _dev_check(keys, payload, merge_cost)
-    if payload is not None and (payload.dtype not in (torch.int32, torch.uint32) or payload.numel() != keys.numel()):
-        raise ValueError("payload must be a 32-bit tensor with one entry per key")
     _check(lib.ps_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None, keys.numel(),
                        _key_type(keys), _opts(min_run, workspace, method, compact_scratch),
                        merge_cost.data_ptr() if merge_cost is not None else None, _stream(stream)))
+    return keys, payload
+
+
+def sort_no_alloc(keys: torch.Tensor, payload: torch.Tensor | None = None, min_run: int | None = None,
+                  merge_cost: torch.Tensor | None = None, stream=None, method: str = "powersort",
+                  compact_scratch: bool = False):
+    """sort() in the library's fixed device scratch (ps_sort_no_alloc): no
+    device allocation, for inputs whose scratch fits 128 MiB.  Calls that
+    overlap on one device race: serialise them (e.g. on one stream)."""
+    lib = load_library()
+    _check_payload(keys, payload)
+    _check_words(merge_cost, "merge_cost", _U64, 1)
+    _dev_check(keys, payload, merge_cost)
+    _check(lib.ps_sort_no_alloc(keys.data_ptr(), payload.data_ptr() if payload is not None else None, keys.numel(),
+                                _key_type(keys), _opts(min_run, None, method, compact_scratch),
+                                merge_cost.data_ptr() if merge_cost is not None else None, _stream(stream)))
     return keys, payload
 
 
@@ -177,8 +222,11 @@ def segmented_sort(keys: torch.Tensor, payload: torch.Tensor | None, offsets: to
                    method: str = "powersort", compact_scratch: bool = False):
     """Sort every segment [offsets[g], offsets[g+1]) independently (offsets: int64 device tensor)."""
     lib = load_library()
+    _check_payload(keys, payload)
+    nseg = _check_offsets(offsets)
+    _check_words(merge_costs, "merge_costs", _U64, nseg)
+    _check_words(status, "status", _I32, 1)
     _dev_check(keys, payload, offsets, merge_costs, status)
-    nseg = offsets.numel() - 1
     _check(lib.ps_segmented_sort(keys.data_ptr(), payload.data_ptr() if payload is not None else None,
                                  offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
                                  _opts(min_run, workspace, method, compact_scratch),
@@ -191,7 +239,8 @@ def merge_cost(keys: torch.Tensor, min_run: int | None = None, out: torch.Tensor
                stream=None, method: str = "powersort") -> torch.Tensor:
     """Merge cost M of powersort (or peeksort) on keys (keys untouched); returns a 1-element int64 device tensor."""
     lib = load_library()
-    _dev_check(keys)
+    _check_words(out, "out", _U64, 1)
+    _dev_check(keys, out)
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=keys.device)
     _check(lib.ps_merge_cost(keys.data_ptr(), keys.numel(), _key_type(keys), _opts(min_run, None, method),
@@ -204,8 +253,10 @@ def segmented_merge_cost(keys: torch.Tensor, offsets: torch.Tensor, min_run: int
                          out: torch.Tensor | None = None, status: torch.Tensor | None = None,
                          stream=None, method: str = "powersort") -> torch.Tensor:
     lib = load_library()
-    _dev_check(keys, offsets)
-    nseg = offsets.numel() - 1
+    nseg = _check_offsets(offsets)
+    _check_words(out, "out", _U64, nseg)
+    _check_words(status, "status", _I32, 1)
+    _dev_check(keys, offsets, out, status)
     if out is None:
         out = torch.empty(nseg, dtype=torch.int64, device=keys.device)
     _check(lib.ps_segmented_merge_cost(keys.data_ptr(), offsets.data_ptr(), nseg, keys.numel(), _key_type(keys),
@@ -219,6 +270,8 @@ def inspect(keys: torch.Tensor, offsets: torch.Tensor | None = None, min_run: in
     """Leaf starts, powers (peeksort: node depth + 1), node leaf ranges and leaf depths
     (as device tensors, trimmed to r)."""
     lib = load_library()
+    if offsets is not None:
+        _check_offsets(offsets)
     _dev_check(keys, offsets)
     n = keys.numel()
     dev = keys.device

@@ -17,23 +17,24 @@ constexpr int kMaskBlockA = kThreads * 16;
 
 // ------------------------------------------------------------ small kernels
 
-// Copies the caller's segment offsets into the workspace, checking that they
-// start at 0, never decrease, end at n_total and describe segments < 2^31.
-// Invalid offsets are replaced by one segment [0, n_total) and reported
-// through the status word (so that no later kernel can index out of bounds).
+// Copies the caller's segment offsets into the workspace, less `base` (the
+// first offset of a chunk of a larger batch), checking that they start at 0,
+// never decrease, end at n_total and describe segments < 2^31.  Invalid
+// offsets are replaced by one segment [0, n_total) and reported through the
+// status word (so that no later kernel can index out of bounds).
 __global__ __launch_bounds__(kThreads) void offsets_kernel(const uint64_t* __restrict__ in, uint32_t nseg,
-                                                            uint64_t N, uint64_t* __restrict__ out,
+                                                            uint64_t N, uint64_t base, uint64_t* __restrict__ out,
                                                             int32_t* __restrict__ status) {
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     int my = 0;
     for (uint32_t g = threadIdx.x; g <= nseg; g += kThreads) {
-        const uint64_t v = in ? in[g] : (g == 0 ? 0 : N);
+        const uint64_t v = in ? in[g] - base : (g == 0 ? 0 : N);
         if (g == 0 && v != 0) my |= 1;
         if (g == nseg && v != N) my |= 1;
         if (g > 0) {
-            const uint64_t u = in ? in[g - 1] : 0;
+            const uint64_t u = in ? in[g - 1] - base : 0;
             if (v < u) my |= 1;
             else if (v - u > kMaxSegment) my |= 2;
         }
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void offsets_kernel(const uint64_t* __res
     if (my) atomicOr(&bad, my);
     __syncthreads();
     for (uint32_t g = threadIdx.x; g <= nseg; g += kThreads) {
-        uint64_t v = in ? in[g] : (g == 0 ? 0 : N);
+        uint64_t v = in ? in[g] - base : (g == 0 ? 0 : N);
         if (bad) v = (g == 0) ? 0 : N;
         out[g] = v;
     }
@@ -305,6 +306,36 @@ static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* o
     return PS_OK;
 }
 
+// --------------------------------------------- fixed scratch (no allocation)
+//
+// ps_sort_no_alloc runs in this array instead of the pool or a caller's
+// workspace.  Each device that loads the library holds its own copy until
+// the process ends.  Host code never uses the array's name as an address:
+// the address on each device comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kFixedScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];  // address of `scratch` on each device
+
+static ps_status fixed_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PS_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(PS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PS_OK;
+}
+
 // ------------------------------------------------------------------ tuning
 
 static std::mutex g_tune_mu;
@@ -355,7 +386,9 @@ struct ProfScope {
     uint64_t elems = 0;
     hipEvent_t a = nullptr;
     hipStream_t st = nullptr;
-    ProfScope(int g, int nl, uint64_t host_elems, hipStream_t s) : group(g), launches(nl), elems(host_elems), st(s) {
+    ProfScope(int g, int nl, uint64_t host_elems, hipStream_t s, bool allowed)
+        : group(g), launches(nl), elems(host_elems), st(s) {
+        if (!allowed) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof.on || !((g_prof.mask >> g) & 1)) return;
         a = prof_event();
@@ -374,7 +407,8 @@ struct ProfScope {
 struct ProfLaunch {
     int group;
     hipEvent_t a = nullptr, b = nullptr;
-    explicit ProfLaunch(int g) : group(g) {
+    ProfLaunch(int g, bool allowed) : group(g) {
+        if (!allowed) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof.on || !((g_prof.mask >> g) & 1)) return;
         a = prof_event();
@@ -421,6 +455,8 @@ struct Call {
     Mode mode;
     bool peek = false;          // PS_FLAG_PEEKSORT: Alg. PeekSort's tree instead of node powers
     uint32_t nbuf = 3;          // data arrays (2 with PS_FLAG_COMPACT_SCRATCH)
+    uint64_t off_base = 0;      // subtracted from d_offsets (a chunk of a larger batch)
+    bool prof = true;           // false: no profiling events (nothing is created or recorded)
 };
 
 static size_t key_bytes(int kt) { return (kt == KT_I64 || kt == KT_U64) ? 8 : 4; }
@@ -469,7 +505,8 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     auto at = [&](size_t off) { return (void*)(base + off); };
 
     uint64_t* offsets = (uint64_t*)at(L.offsets);
-    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, nseg, c.N, offsets, c.d_status);
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, nseg, c.N, c.off_base, offsets,
+                       c.d_status);
     Counters* cnt = (Counters*)at(L.counters);
     uint64_t* mc = (uint64_t*)at(L.mc);
     hipError_t e = launch_init(cnt, mc, nseg, st);
@@ -495,7 +532,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     pa.r_dev = (uint32_t*)cnt;  // Counters.r is its first word
     pa.rmax = L.rmax;
     {
-        ProfScope ps_(PS_PROF_PARTITION, 2 + 2 * L.levels, c.N, st);
+        ProfScope ps_(PS_PROF_PARTITION, 2 + 2 * L.levels, c.N, st, c.prof);
         e = launch_partition(c.kt, pa, st);
     }
     if (e != hipSuccess) return hip_fail(e, "partition launch");
@@ -524,11 +561,11 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     // that many + 1 levels build the whole tree (the key bound of kMaxPass).
     const uint32_t peek_levels = std::max<uint32_t>(1, 2 * ilog2_floor(c.N));
     if (c.peek) {
-        ProfScope ps_(PS_PROF_TREE, 1 + peek_levels, c.N, st);
+        ProfScope ps_(PS_PROF_TREE, 1 + peek_levels, c.N, st, c.prof);
         e = launch_peek_tree(ta, (PeekRange*)at(L.peek_f[0]), (PeekRange*)at(L.peek_f[1]), L.peek_cap, peek_levels,
                              st);
     } else {
-        ProfScope ps_(PS_PROF_TREE, 4, c.N, st);
+        ProfScope ps_(PS_PROF_TREE, 4, c.N, st, c.prof);
         e = launch_tree_cost(ta, st);
     }
     if (e != hipSuccess) return hip_fail(e, "tree launch");
@@ -548,12 +585,12 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
         ta.lists.leaf_tile = (uint32_t*)at(L.leaf_tile);
         ta.lists.nbuf = c.nbuf;
-        if (prof_on()) {
+        if (c.prof && prof_on()) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             ta.prof = g_prof.dev;
         }
         {
-            ProfScope ps_(PS_PROF_LISTS, c.peek ? 5 : 6, c.N, st);
+            ProfScope ps_(PS_PROF_LISTS, c.peek ? 5 : 6, c.N, st, c.prof);
             if (!c.peek) e = launch_node_ranges(ta, st);
             if (e == hipSuccess) e = launch_tree_lists(c.kt, ta, st);
         }
@@ -604,7 +641,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         const uint64_t max_units = c.N / 2 + 1;
         const uint32_t grid_fuse = (uint32_t)std::min<uint64_t>(max_units, tune.grid_fused);
         auto stage = [&](int group, int s, uint32_t p, uint32_t grid) {
-            ProfLaunch pl(group);
+            ProfLaunch pl(group, c.prof);
             const hipError_t r = launch_move_stage(c.kt, hp, ma, s, p, grid, st, pl.a, pl.b);
             pl.done(r);
             return r;
@@ -620,7 +657,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
             if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
-        if (prof_on()) {
+        if (c.prof && prof_on()) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             g_prof.totals.calls++;
         }
@@ -657,8 +694,8 @@ static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st)
     uint64_t* offsets = (uint64_t*)((char*)ws + L.offsets);
     uint64_t* mc = (uint64_t*)((char*)ws + L.mc);
     Counters* cnt = (Counters*)((char*)ws + L.counters);
-    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, (uint32_t)c.nseg, 0ull, offsets,
-                       c.d_status);
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, st, c.d_offsets, (uint32_t)c.nseg, 0ull,
+                       c.off_base, offsets, c.d_status);
     hipError_t e = launch_init(cnt, mc, (uint32_t)c.nseg, st);
     if (e != hipSuccess) return hip_fail(e, "init launch");
     if (c.d_costs)
@@ -670,6 +707,60 @@ static ps_status run_empty(const Call& c, const ps_options* opt, hipStream_t st)
     return PS_OK;
 }
 
+// A segmented call above kMaxTotal elements.  Every kernel indexes positions
+// in u32, so the batch is cut at segment boundaries into consecutive chunks
+// of at most kMaxTotal elements (greedily, left to right; every segment is
+// below 2^31, so each chunk holds at least one), which run one after another
+// on the stream in one workspace sized for the largest.  Choosing the cuts
+// needs the offsets on the host: they are read back once, which
+// synchronises the stream, and validated there (an invalid batch returns its
+// error with nothing further enqueued).
+static ps_status run_chunked(const Call& c, const ps_options* opt, hipStream_t st) {
+    std::vector<uint64_t> h((size_t)c.nseg + 1);
+    hipError_t e = hipMemcpyAsync(h.data(), c.d_offsets, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reading the segment offsets");
+    if (h[0] != 0 || h[c.nseg] != c.N)
+        return fail(PS_ERR_INVALID_ARG, "segment offsets must start at 0 and end at n_total");
+    for (uint64_t g = 0; g < c.nseg; ++g) {
+        if (h[g + 1] < h[g]) return fail(PS_ERR_INVALID_ARG, "segment offsets decrease");
+        if (h[g + 1] - h[g] > kMaxSegment) return fail(PS_ERR_TOO_LARGE, "a segment holds 2^31 or more elements");
+    }
+    const size_t kb = key_bytes(c.kt);
+    const bool moves = (c.mode == Mode::Sort);
+    const bool hp = moves && c.payload != nullptr;
+    std::vector<std::pair<uint64_t, uint64_t>> chunks;  // segment ranges [g0, g1)
+    size_t need = 0;
+    for (uint64_t g0 = 0; g0 < c.nseg;) {
+        uint64_t g1 = g0 + 1;
+        while (g1 < c.nseg && h[g1 + 1] - h[g0] <= kMaxTotal) ++g1;
+        chunks.emplace_back(g0, g1);
+        need = std::max(need, make_layout(h[g1] - h[g0], g1 - g0, kb, hp, c.w, moves, c.peek, c.nbuf).total);
+        g0 = g1;
+    }
+    void* ws = nullptr;
+    ps_status s = get_workspace(st, need, opt, &ws);
+    if (s != PS_OK) return s;
+    ps_options one{};
+    one.struct_size = sizeof(ps_options);
+    one.workspace = ws;
+    one.workspace_bytes = need;
+    for (const auto& ch : chunks) {
+        Call cc = c;
+        const uint64_t base = h[ch.first];
+        cc.keys = (char*)c.keys + base * kb;
+        cc.payload = c.payload ? c.payload + base : nullptr;
+        cc.d_offsets = c.d_offsets + ch.first;
+        cc.nseg = ch.second - ch.first;
+        cc.N = h[ch.second] - base;
+        cc.off_base = base;
+        cc.d_costs = c.d_costs ? c.d_costs + ch.first : nullptr;
+        s = cc.N == 0 ? run_empty(cc, &one, st) : run(cc, &one, st);
+        if (s != PS_OK) return s;
+    }
+    return PS_OK;
+}
+
 static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     g_last_error.clear();
     CallOpts o;
@@ -678,14 +769,17 @@ static ps_status dispatch(Call c, const ps_options* opt, void* stream) {
     c.w = o.w;
     c.peek = o.peek;
     c.nbuf = o.nbuf;
-    if (c.N > kMaxTotal) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^31");
     if (c.nseg == 0) return fail(PS_ERR_INVALID_ARG, "num_segments must be at least 1");
     if (c.nseg >= kMaxTotal) return fail(PS_ERR_TOO_LARGE, "too many segments");
     if (!c.d_offsets && c.nseg != 1) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
     if (!c.d_offsets && c.N > kMaxSegment) return fail(PS_ERR_TOO_LARGE, "n must be below 2^31");
+    if (c.N > kMaxBatch) return fail(PS_ERR_TOO_LARGE, "n_total must be below 2^63");
+    if (c.N > kMaxTotal && c.mode == Mode::Inspect)
+        return fail(PS_ERR_TOO_LARGE, "ps_inspect takes n_total below 2^31 (leaf starts are 32-bit)");
     if (c.N > 0 && !c.keys) return fail(PS_ERR_INVALID_ARG, "keys is NULL");
     hipStream_t st = (hipStream_t)stream;
     if (c.N == 0) return run_empty(c, opt, st);
+    if (c.N > kMaxTotal) return run_chunked(c, opt, st);
     return run(c, opt, st);
 }
 
@@ -793,8 +887,12 @@ size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type k
                           const ps_options* opt) {
     CallOpts o;
     if (check_common((int)key_type, opt, &o) != PS_OK) return 0;
-    if (n_total > kMaxTotal || num_segments == 0 || num_segments >= kMaxTotal) return 0;
-    return make_layout(n_total, num_segments, key_bytes((int)key_type), has_payload != 0, o.w, true, o.peek, o.nbuf)
+    if (n_total > kMaxBatch || num_segments == 0 || num_segments >= kMaxTotal) return 0;
+    if (num_segments == 1 && n_total > kMaxSegment) return 0;
+    // above kMaxTotal the batch runs in chunks of at most kMaxTotal elements
+    // (ps_segmented_sort), each needing no more than this
+    return make_layout(std::min(n_total, kMaxTotal), num_segments, key_bytes((int)key_type), has_payload != 0, o.w,
+                       true, o.peek, o.nbuf)
         .total;
 }
 
@@ -813,6 +911,35 @@ ps_status ps_sort(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_typ
                   uint64_t* d_merge_cost, void* stream) {
     Call c{keys, payload, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
     return dispatch(c, opt, stream);
+}
+
+ps_status ps_sort_no_alloc(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_type, const ps_options* opt,
+                           uint64_t* d_merge_cost, void* stream) {
+    g_last_error.clear();
+    CallOpts o;
+    ps_status s = check_common((int)key_type, opt, &o);
+    if (s != PS_OK) return s;
+    if (opt && opt->workspace)
+        return fail(PS_ERR_INVALID_ARG, "ps_sort_no_alloc runs in the library's fixed scratch: "
+                                        "ps_options.workspace must be NULL");
+    if (n > kMaxSegment) return fail(PS_ERR_TOO_LARGE, "n must be below 2^31");
+    if (n > 0 && !keys) return fail(PS_ERR_INVALID_ARG, "keys is NULL");
+    const size_t need =
+        make_layout(n, 1, key_bytes((int)key_type), payload != nullptr, o.w, true, o.peek, o.nbuf).total;
+    if (need > kFixedScratchBytes)
+        return fail(PS_ERR_TOO_LARGE, "this sort needs " + std::to_string(need) +
+                                          " bytes of scratch; the fixed scratch holds " +
+                                          std::to_string(kFixedScratchBytes));
+    void* ptr = nullptr;
+    s = fixed_scratch(&ptr);
+    if (s != PS_OK) return s;
+    ps_options fixed = opt ? *opt : ps_options{};
+    fixed.struct_size = sizeof(ps_options);
+    fixed.workspace = ptr;
+    fixed.workspace_bytes = kFixedScratchBytes;
+    Call c{keys, payload, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
+    c.prof = false;
+    return dispatch(c, &fixed, stream);
 }
 
 ps_status ps_segmented_sort(void* keys, uint32_t* payload, const uint64_t* d_offsets, uint64_t num_segments,

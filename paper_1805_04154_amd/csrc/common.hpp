@@ -120,8 +120,11 @@ constexpr int kMaxPass = 64;
 // Per-call limits.
 constexpr uint64_t kMaxSegment = (1ull << 31) - 1;
 // Positions are u32 in every kernel: below 2^31, a position plus any
-// grid stride or tile length stays below 2^32, so no index can wrap.
+// grid stride or tile length stays below 2^32, so no index can wrap.  A
+// segmented batch above this runs as consecutive chunks of at most
+// kMaxTotal elements, cut at segment boundaries.
 constexpr uint64_t kMaxTotal = (1ull << 31) - 1;
+constexpr uint64_t kMaxBatch = (1ull << 63) - 1;  // n_total of a segmented batch
 constexpr uint64_t kMaxTreeLeaves = 1ull << 28;  // leaves of ps_alphabetic_tree
 
 __device__ __forceinline__ int clz32(uint32_t x) { return __clz(x); }

@@ -51,13 +51,20 @@ def test_argument_validation_without_launch(lib):
     assert lib.ps_sort(fake, None, 1 << 31, 0, None, None, None) == -2
     assert lib.ps_segmented_sort(fake, None, None, 3, 10, 0, None, None, None, None) == -1
     assert lib.ps_segmented_sort(fake, None, fake, 0, 10, 0, None, None, None, None) == -1
-    assert lib.ps_segmented_sort(fake, None, fake, 2, 1 << 32, 0, None, None, None, None) == -2
-    # u32 positions: n_total itself must stay below 2^31
-    assert lib.ps_segmented_sort(fake, None, fake, 2, 1 << 31, 0, None, None, None, None) == -2
-    assert b"2^31" in lib.ps_last_error()
-    assert lib.ps_segmented_merge_cost(fake, fake, 2, 1 << 31, 0, None, fake, None, None) == -2
-    assert lib.ps_workspace_bytes(1 << 31, 2, 0, 1, None) == 0
+    # a segmented batch may hold up to 2^63 - 1 keys in all (chunked above
+    # 2^31 - 1); one array stays below 2^31
+    assert lib.ps_segmented_sort(fake, None, fake, 2, 1 << 63, 0, None, None, None, None) == -2
+    assert b"2^63" in lib.ps_last_error()
+    assert lib.ps_segmented_merge_cost(fake, fake, 2, 1 << 63, 0, None, fake, None, None) == -2
+    assert lib.ps_inspect(fake, fake, 2, 1 << 31, 0, None, ctypes.byref(binding.PsInspectOut()), None) == -2
+    assert lib.ps_merge_cost(fake, 1 << 31, 0, None, fake, None) == -2
+    assert lib.ps_workspace_bytes(1 << 31, 1, 0, 1, None) == 0
     assert lib.ps_workspace_bytes((1 << 31) - 1, 2, 0, 1, None) > 0
+    # above 2^31 - 1 keys the batch runs in chunks below 2^31: the workspace
+    # is that of the largest possible chunk
+    assert lib.ps_workspace_bytes(1 << 31, 2, 0, 1, None) == lib.ps_workspace_bytes((1 << 31) - 1, 2, 0, 1, None)
+    assert lib.ps_workspace_bytes(1 << 40, 2, 0, 1, None) == lib.ps_workspace_bytes((1 << 31) - 1, 2, 0, 1, None)
+    assert lib.ps_workspace_bytes(1 << 63, 2, 0, 1, None) == 0
     assert lib.ps_merge_cost(fake, 10, 0, None, None, None) == -1
     assert lib.ps_segmented_merge_cost(fake, fake, 2, 10, 0, None, None, None, None) == -1
     assert lib.ps_inspect(fake, None, 1, 10, 0, None, None, None) == -1
@@ -110,3 +117,74 @@ def test_tuning_roundtrip_on_host():
         binding.set_tuning({"grid_split": 1 << 20})
     binding.set_tuning(None)
     assert binding.get_tuning() == d
+
+
+def test_no_alloc_entry_point_rejects_before_launch(lib):
+    """ps_sort_no_alloc checks its limit and options before touching a device."""
+    from paper_1805_04154_amd import binding
+    fake = ctypes.c_void_p(0x1000)
+    cap = 128 << 20
+    # largest n whose scratch fits the fixed 128 MiB array, int32 keys + payload
+    lo, hi = 1, 1 << 31
+    while lo < hi:
+        m = (lo + hi + 1) // 2
+        if lib.ps_workspace_bytes(m, 1, 0, 1, None) <= cap:
+            lo = m
+        else:
+            hi = m - 1
+    assert lo > 6_000_000
+    assert lib.ps_sort_no_alloc(fake, fake, lo + 1, 0, None, None, None) == -2
+    assert b"fixed scratch" in lib.ps_last_error()
+    assert lib.ps_sort_no_alloc(fake, None, 1 << 31, 0, None, None, None) == -2
+    o = binding.PsOptions(ctypes.sizeof(binding.PsOptions), 0, 0, 0, 0x2000, 1 << 30)
+    assert lib.ps_sort_no_alloc(fake, fake, 100, 0, ctypes.byref(o), None, None) == -1
+    assert b"workspace" in lib.ps_last_error()
+    assert lib.ps_sort_no_alloc(fake, None, 10, 0, _opts(binding, min_run=65), None, None) == -5
+    assert lib.ps_sort_no_alloc(None, None, 10, 0, None, None, None) == -1
+
+
+def test_binding_rejects_mismatched_tensors():
+    """The binding checks sizes and dtypes of every array the library would
+    index before anything reaches the device."""
+    import torch
+    from paper_1805_04154_amd import binding
+    k = torch.zeros(10, dtype=torch.int32)
+    off = torch.tensor([0, 4, 10], dtype=torch.int64)
+    pay_short = torch.zeros(9, dtype=torch.int32)
+    with pytest.raises(ValueError, match="payload"):
+        binding.segmented_sort(k, pay_short, off)
+    with pytest.raises(ValueError, match="payload"):
+        binding.segmented_sort(k, torch.zeros(10, dtype=torch.int64), off)
+    with pytest.raises(ValueError, match="payload"):
+        binding.sort(k, pay_short)
+    with pytest.raises(ValueError, match="payload"):
+        binding.sort_no_alloc(k, pay_short)
+    with pytest.raises(ValueError, match="offsets"):
+        binding.segmented_sort(k, None, off.to(torch.int32))
+    with pytest.raises(ValueError, match="offsets"):
+        binding.segmented_sort(k, None, torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="offsets"):
+        binding.segmented_sort(k, None, off.view(1, 3))
+    with pytest.raises(ValueError, match="merge_costs"):
+        binding.segmented_sort(k, None, off, merge_costs=torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="merge_costs"):
+        binding.segmented_sort(k, None, off, merge_costs=torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError, match="status"):
+        binding.segmented_sort(k, None, off, status=torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="status"):
+        binding.segmented_sort(k, None, off, status=torch.zeros(0, dtype=torch.int32))
+    with pytest.raises(ValueError, match="merge_cost"):
+        binding.sort(k, None, merge_cost=torch.zeros(1, dtype=torch.int32))
+    with pytest.raises(ValueError, match="out"):
+        binding.merge_cost(k, out=torch.zeros(0, dtype=torch.int64))
+    with pytest.raises(ValueError, match="out"):
+        binding.segmented_merge_cost(k, off, out=torch.zeros(1, dtype=torch.int64))
+    with pytest.raises(ValueError, match="status"):
+        binding.segmented_merge_cost(k, off, status=torch.zeros(1, dtype=torch.float32))
+    with pytest.raises(ValueError, match="offsets"):
+        binding.inspect(k, offsets=off.to(torch.int32))
+    # well-formed host tensors get as far as the device check
+    with pytest.raises(ValueError, match="GPU"):
+        binding.segmented_sort(k, torch.zeros(10, dtype=torch.int32), off,
+                               merge_costs=torch.zeros(2, dtype=torch.int64),
+                               status=torch.zeros(1, dtype=torch.int32))

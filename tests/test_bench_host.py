@@ -13,12 +13,7 @@ import bench  # noqa: E402
 
 
 def committed_fields():
-    fields = {}
-    for line in open(bench.COUNTERS_MD).read().splitlines():
-        if line.startswith("- ") and ": " in line:
-            k, v = line[2:].split(": ", 1)
-            fields[k.strip()] = v.strip().strip("`")
-    return fields
+    return bench.profile_fields(bench.COUNTERS_MD)
 
 
 def test_traffic_gate_matches_only_what_was_measured():
@@ -64,3 +59,36 @@ def test_batched_and_served_oracle_baselines():
     keys = W.materialize(metas, workers=1)
     s = bench.served_cpu_baseline(keys, 1.0)
     assert s["service_ms"]["p50"] <= s["service_ms"]["p99"] and s["value"] > 0
+
+
+def test_trace_gate_matches_only_what_was_traced():
+    f = bench.profile_fields(bench.TRACE_MD)
+    if "merge_pass_average_ns" not in f:
+        assert bench.traced_launch_ms("zipf_runs_n268435456_int32", 8192) is None
+        return
+    got = bench.traced_launch_ms(f["workload"], int(f["merge_tile"]))
+    if f["kernel_source_digest"] != bench.merge_kernel_digest():
+        assert got is None
+        return
+    assert got == float(f["merge_pass_average_ns"]) / 1e6
+    assert bench.traced_launch_ms(f["workload"] + "_other", int(f["merge_tile"])) is None
+
+
+def test_oracle_runs_pinned_with_warmup_and_median():
+    import os
+    from paper_1805_04154_amd import workloads as W
+    seen = []
+    _, core = bench.run_pinned(lambda: seen.append(os.sched_getaffinity(0)))
+    assert seen == [{core}]
+    assert os.sched_getaffinity(0) != {core} or len(bench.usable_cores()) == 1  # the caller is not pinned
+    wl = W.runs_2p20(n=1 << 16)
+    r = bench.cpu_baseline(wl, "powersort", reps=3)
+    assert r["cores"] == 1 and r["kind"] == "oracle" and len(r["times_s"]) == 3
+    assert r["merge_costs_agree"] and r["merge_cost"] > 0
+    assert abs(r["median_s"] - sorted(r["times_s"])[1]) < 1e-3
+
+
+def test_latency_percentiles():
+    p = bench.latency_ms([0.001 * i for i in range(1, 101)])
+    assert p["sorts"] == 100 and p["min"] == 1.0 and p["max"] == 100.0
+    assert p["p50"] == 50.5 and abs(p["p99"] - 99.01) < 1e-9

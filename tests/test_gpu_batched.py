@@ -104,3 +104,43 @@ def test_autotuner_picks_a_candidate_and_keeps_results(setup, tmp_path):
         assert np.array_equal(to_host(b.payload, np.uint32), rp)
     finally:
         binding.set_tuning(None)
+
+
+def test_single_sort_graph_replays_match_eager(setup):
+    """One ps_sort with a caller workspace captured as a graph (as the
+    single-sort latency benchmark does) and replayed four times, with eager
+    work and synchronisations between replays: every replay equals the
+    oracle."""
+    import torch
+    import oracle
+    batched, binding, wl, _ = setup
+    one = W.runs_2p20(n=(1 << 20) + 3)
+    ref = oracle.powersort(one.keys, one.payload, details=False)
+    src_k, src_p = to_dev(one.keys), to_dev(one.payload)
+    k, p = src_k.clone(), src_p.clone()
+    M = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(binding.workspace_bytes(one.n, 1, torch.int32, True), dtype=torch.uint8, device="cuda")
+    binding.sort(k, p, merge_cost=M, workspace=ws)  # eager warm-up
+    torch.cuda.synchronize()
+    k.copy_(src_k)
+    p.copy_(src_p)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        binding.sort(k, p, merge_cost=M, workspace=ws)
+    torch.cuda.synchronize()
+    other = to_dev(W.random_permutation(W.make_rng(78), 30000).astype(np.int32))
+    for rep in range(4):
+        k.copy_(src_k)
+        p.copy_(src_p)
+        M.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(k, np.int32), ref.keys), f"replay {rep}"
+        assert np.array_equal(to_host(p, np.uint32), ref.payload), f"replay {rep}"
+        assert int(M.item()) == ref.merge_cost, f"replay {rep}"
+        o = other.clone()
+        binding.sort(o)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert bool((o[1:] >= o[:-1]).all())

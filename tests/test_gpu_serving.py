@@ -102,8 +102,8 @@ def test_tight_budget_and_plain(trace):
     biggest = max(m.n for m in metas)
     reqs = make_requests(metas, keys, torch)
     # room for one or two requests at a time: admission waits for memory
-    srv = serving.SortServer(hbm_budget_bytes=2 * serving.BYTES_PER_KEY * biggest + (1 << 20),
-                                slots=2)
+    srv = serving.SortServer(hbm_budget_bytes=2 * serving.batch_bytes(biggest, 1, torch.int64, False) + (1 << 20),
+                             slots=2)
     done = srv.serve(reqs, realtime=False)
     torch.cuda.synchronize()
     check(done, refs, keys)
@@ -119,7 +119,7 @@ def test_oversized_request_is_rejected(trace):
     metas, keys, refs = trace
     big = max(range(len(metas)), key=lambda i: metas[i].n)
     reqs = make_requests([metas[big]], [keys[big]], torch)
-    srv = serving.SortServer(hbm_budget_bytes=serving.BYTES_PER_KEY * (metas[big].n // 2), slots=1)
+    srv = serving.SortServer(hbm_budget_bytes=serving.batch_bytes(metas[big].n // 2, 1, torch.int32, True), slots=1)
     with pytest.raises(ValueError):
         srv.serve(reqs, realtime=False)
 
@@ -131,7 +131,8 @@ def test_pool_requests_sorted_in_place(trace):
     from paper_1805_04154_amd import serving
     metas, keys, refs = trace
     biggest = max(m.n for m in metas)
-    for budget, slots in ((1 << 30, 2), (2 * serving.BYTES_PER_KEY * biggest + (1 << 20), 2), (1 << 30, 1)):
+    tight = 2 * serving.batch_bytes(biggest, 1, torch.int64, True) + (1 << 20)
+    for budget, slots in ((1 << 30, 2), (tight, 2), (1 << 30, 1)):
         reqs = make_pool_requests(metas, keys, torch)
         done = serving.SortServer(hbm_budget_bytes=budget, slots=slots).serve(reqs, realtime=False)
         torch.cuda.synchronize()
@@ -151,5 +152,85 @@ def test_pool_and_plain_requests_mixed(trace):
     own = make_requests(metas, keys, torch)
     reqs = [own[i] if i % 3 == 0 else pooled[i] for i in range(len(metas))]
     done = serving.SortServer(hbm_budget_bytes=1 << 30, slots=2).serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+
+
+def test_admission_waits_for_memory_with_a_slot_idle():
+    """Four equal requests, each needing B bytes of arena, under a budget of
+    1.5 B and two slots: only one batch fits at a time, so the second slot
+    stays idle while the first holds the memory, and every result is still
+    the oracle's."""
+    import torch
+    import oracle
+    from paper_1805_04154_amd import batched, serving
+    n = 1 << 16
+    rng = W.make_rng(77)
+    keys = [W.random_runs(rng, n, 256.0, 0.25).astype(np.int32) for _ in range(4)]
+    refs = [oracle.powersort(k, W.payload_for(n)) for k in keys]
+    reqs = [serving.ServedRequest(i, 0.0, batched.to_device(k), batched.to_device(W.payload_for(n)))
+            for i, k in enumerate(keys)]
+    one = serving.batch_bytes(n, 1, torch.int32, False)
+    assert serving.batch_bytes(2 * n, 2, torch.int32, False) > one * 3 // 2
+    srv = serving.SortServer(hbm_budget_bytes=one * 3 // 2, slots=2)
+    done = srv.serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+    assert srv.stats["batches"] == 4
+    assert srv.stats["max_inflight"] == 1
+    assert srv.stats["memory_waits"] > 0
+    assert srv.stats["peak_bytes"] <= srv.budget
+    # with room for two, both slots are used
+    srv2 = serving.SortServer(hbm_budget_bytes=2 * one + (1 << 20), slots=2, max_batch_keys=n)
+    reqs = [serving.ServedRequest(i, 0.0, batched.to_device(k), batched.to_device(W.payload_for(n)))
+            for i, k in enumerate(keys)]
+    done = srv2.serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+    assert srv2.stats["max_inflight"] == 2
+
+
+def real_size_trace():
+    """Thirty requests at the served workload's real sizes (log-uniform in
+    [2^12, 2^24]) and key types, with an int64 request of 2^24 keys, a
+    float32 request above 2^22 and an int64 request above 2^22 forced in."""
+    metas = W.trace_meta(rate_hz=2000, duration_s=1.0, lo_exp=12, hi_exp=24, seed_index=21, max_requests=30)
+    forced = {3: (1 << 24, np.int64), 11: ((1 << 22) + 4097, np.float32), 19: ((1 << 22) + 123, np.int64),
+              25: ((1 << 23) - 5, np.int32)}
+    for i, (n, dt) in forced.items():
+        metas[i].n, metas[i].dtype = n, np.dtype(dt)
+    return metas
+
+
+def test_real_size_requests_alone_and_in_the_mix():
+    import concurrent.futures as cf
+    import torch
+    import oracle
+    from paper_1805_04154_amd import serving
+    metas = real_size_trace()
+    print(f"serving parity at real sizes: {len(metas)} requests, {sum(m.n for m in metas)} keys", flush=True)
+    keys = W.materialize(metas, workers=1)
+    assert {k.dtype for k in keys} == {np.dtype(np.int32), np.dtype(np.int64), np.dtype(np.float32)}
+    assert max(m.n for m in metas) == 1 << 24
+    with cf.ThreadPoolExecutor(8) as ex:
+        refs = list(ex.map(lambda k: oracle.powersort(k, W.payload_for(len(k)), details=False), keys))
+    # in the mix: pool requests sorted in place and gathered requests, two slots
+    pooled = make_pool_requests(metas, keys, torch)
+    own = make_requests(metas, keys, torch)
+    mixed = [own[i] if i % 4 == 0 else pooled[i] for i in range(len(metas))]
+    srv = serving.SortServer(hbm_budget_bytes=8 << 30, slots=2)
+    done = srv.serve(mixed, realtime=False)
+    torch.cuda.synchronize()
+    check(done, refs, keys)
+    assert srv.stats["batches"] < len(metas)  # requests were batched
+    # alone: one request per server call
+    for i in range(len(metas)):
+        alone = make_requests([metas[i]], [keys[i]], torch)
+        alone[0].rid = 0
+        serving.SortServer(hbm_budget_bytes=2 << 30, slots=1).serve(alone, realtime=False)
+        torch.cuda.synchronize()
+        check(alone, [refs[i]], [keys[i]])
+    # the plain per-request path too
+    done = serving.serve_plain(make_requests(metas, keys, torch), realtime=False)
     torch.cuda.synchronize()
     check(done, refs, keys)

@@ -152,3 +152,23 @@ def test_every_node_power_is_within_the_pass_bound(w):
     # and the bound is attained up to one level on a permutation
     ref = oracle.powersort(W.random_permutation(rng, 1 << 16).astype(np.int32), None, min_run=w)
     assert int(ref.powers.max()) >= pass_bound(1 << 16, w) - 1
+
+
+def test_arena_allocator_first_fit_and_coalescing():
+    from paper_1805_04154_amd.serving import ALIGN, ArenaAllocator
+    a = ArenaAllocator(10 * ALIGN)
+    x = a.alloc(3 * ALIGN)
+    y = a.alloc(ALIGN + 1)        # rounded up to 2 units
+    z = a.alloc(4 * ALIGN)
+    assert (x, y, z) == (0, 3 * ALIGN, 5 * ALIGN)
+    assert a.in_use == 9 * ALIGN and a.largest_free() == ALIGN
+    assert a.alloc(2 * ALIGN) is None  # one unit left
+    a.release(y, ALIGN + 1)
+    assert a.largest_free() == 2 * ALIGN and a.alloc(2 * ALIGN) == 3 * ALIGN
+    a.release(3 * ALIGN, 2 * ALIGN)
+    a.release(x, 3 * ALIGN)            # coalesces with the freed block on its right
+    assert a.free[0] == (0, 5 * ALIGN)
+    a.release(z, 4 * ALIGN)            # and everything merges back into one block
+    assert a.free == [(0, 10 * ALIGN)] and a.in_use == 0
+    with pytest.raises(ValueError):
+        a.release(0, ALIGN)            # not allocated

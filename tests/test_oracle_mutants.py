@@ -56,11 +56,30 @@ PEEK_MUTANTS = {
 }
 
 
+# Mistakes in the elementary mergesorts, checked against their pins.
+MERGESORT_MUTANTS = {
+    # the check merges runs that meet in equal keys (they are in order)
+    "mergesort_check_nonstrict": ("    if (less_at(A, mid, mid - 1)) {  /* not already in order */",
+                                  "    if (!less_at(A, mid - 1, mid)) {  /* not already in order */"),
+    # the left half takes the floor of half the elements
+    "topdown_split_floor": ("uint64_t mid = lo + (hi - lo + 1) / 2;", "uint64_t mid = lo + (hi - lo) / 2;"),
+    # insertion sort only below w (pieces of exactly w are split once more)
+    "topdown_cutoff_strict": ("    if (hi - lo <= w) {\n        insertion_sort(A, lo, hi, 0);",
+                              "    if (hi - lo < w) {\n        insertion_sort(A, lo, hi, 0);"),
+    # bottom-up run lengths start at 2w
+    "bottomup_first_level_skipped": ("for (uint64_t m = w; m < n; m *= 2) {", "for (uint64_t m = 2 * w; m < n; m *= 2) {"),
+}
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PEEK_MUTANTS))
+@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PEEK_MUTANTS) + sorted(MERGESORT_MUTANTS))
 def test_pins_reject_planted_mistake(tmp_path, name):
-    a, b = MUTANTS[name] if name in MUTANTS else PEEK_MUTANTS[name]
-    suite = "tests/test_oracle_pins.py" if name in MUTANTS else "tests/test_oracle_peeksort.py"
+    if name in MUTANTS:
+        (a, b), suite = MUTANTS[name], "tests/test_oracle_pins.py"
+    elif name in PEEK_MUTANTS:
+        (a, b), suite = PEEK_MUTANTS[name], "tests/test_oracle_peeksort.py"
+    else:
+        (a, b), suite = MERGESORT_MUTANTS[name], "tests/test_oracle_mergesorts.py"
     src = open(os.path.join(ROOT, "oracle", "powersort_oracle.c")).read()
     assert a in src, "mutation site not found"
     ign = shutil.ignore_patterns("*.so", "*.tmp", "__pycache__")
@@ -70,4 +89,5 @@ def test_pins_reject_planted_mistake(tmp_path, name):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         suite], cwd=tmp_path, capture_output=True, text=True,
                        timeout=600)
-    assert r.returncode == 1, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
+    # 1: a pin failed; a signal: the mutant crashed the suite (e.g. endless recursion)
+    assert r.returncode == 1 or r.returncode < 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
