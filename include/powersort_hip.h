@@ -272,6 +272,14 @@ ps_status ps_profile_enable(int on);
  * *out; reset != 0 clears the totals afterwards. */
 ps_status ps_profile_read(ps_profile *out, int reset);
 
+/* Cap the scratch the library's per-stream pool may hold for one stream
+ * (bytes; 0 = no cap, the default).  A call whose scratch (as given by
+ * ps_workspace_bytes) exceeds the cap returns PS_ERR_OUT_OF_MEMORY with
+ * nothing enqueued, as it would if the allocation failed; calls with a
+ * caller workspace or through ps_sort_no_alloc are not affected.  Existing
+ * pool entries are kept until they must grow.  Process-wide. */
+ps_status ps_set_pool_limit(uint64_t bytes);
+
 /* Free the scratch memory the library holds for `stream` (synchronises it). */
 ps_status ps_release(void *stream);
 

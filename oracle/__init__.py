@@ -57,8 +57,31 @@ class _Merge(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("mid", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
 
 
+_SAN_LIB_PATH = os.path.join(_HERE, "liboracle_san.so")
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build_sanitized() -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc) into oracle/liboracle_san.so.  Loading it needs gcc's libasan
+    preloaded (see asan_runtime()); select it with ORACLE_LIB."""
+    tmp = _SAN_LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", *SANITIZE_FLAGS,
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _SAN_LIB_PATH)
+    return _SAN_LIB_PATH
+
+
+def asan_runtime() -> str:
+    """Path of gcc's AddressSanitizer runtime, for LD_PRELOAD."""
+    return subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc -O2 into oracle/liboracle.so."""
+    """Compile the oracle with gcc -O2 into oracle/liboracle.so (or, with
+    ORACLE_LIB set in the environment, use that prebuilt library instead)."""
+    if os.environ.get("ORACLE_LIB"):
+        return os.environ["ORACLE_LIB"]
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",

@@ -13,7 +13,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpowersort_hip.so")
+# The in-tree build; POWERSORT_HIP_LIB may name another build of the same
+# library (e.g. one with host-side sanitizers for the ABI checks).
+LIB_PATH = os.environ.get("POWERSORT_HIP_LIB") or os.path.join(_HERE, "libpowersort_hip.so")
 
 PS_OK = 0
 STATUS_NAMES = {0: "PS_OK", -1: "PS_ERR_INVALID_ARG", -2: "PS_ERR_TOO_LARGE", -3: "PS_ERR_OUT_OF_MEMORY",
@@ -24,7 +26,7 @@ KEY_TYPES = {torch.int32: 0, torch.uint32: 1, torch.int64: 2, torch.uint64: 3, t
 EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_sort_no_alloc", "ps_segmented_sort", "ps_merge_cost",
            "ps_segmented_merge_cost",
            "ps_inspect", "ps_alphabetic_tree", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable",
-           "ps_profile_read", "ps_release",
+           "ps_profile_read", "ps_set_pool_limit", "ps_release",
            "ps_status_string", "ps_last_error")
 TUNING_FIELDS = ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split", "merge_tile")
 PROF_GROUPS = ("partition", "tree", "lists", "big_leaf", "fused", "merge", "split")
@@ -95,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.ps_profile_enable.argtypes = [i32]
     lib.ps_profile_read.restype = i32
     lib.ps_profile_read.argtypes = [ctypes.POINTER(PsProfile), i32]
+    lib.ps_set_pool_limit.restype = i32
+    lib.ps_set_pool_limit.argtypes = [u64]
     lib.ps_release.restype = i32
     lib.ps_release.argtypes = [vp]
     lib.ps_status_string.restype = ctypes.c_char_p
@@ -360,6 +364,12 @@ def profile_read(reset: bool = False) -> dict:
     _check(lib.ps_profile_read(ctypes.byref(p), int(reset)))
     return {"calls": p.calls,
             **{g: {"launches": p.launches[i], "ms": p.ms[i], "elems": p.elems[i]} for i, g in enumerate(PROF_GROUPS)}}
+
+
+def set_pool_limit(nbytes: int):
+    """Cap the library's per-stream scratch (0 = no cap): larger calls fail
+    with PS_ERR_OUT_OF_MEMORY before anything is enqueued."""
+    _check(load_library().ps_set_pool_limit(int(nbytes)))
 
 
 def release(stream=None):

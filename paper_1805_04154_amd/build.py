@@ -50,6 +50,45 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
     return LIB_PATH
 
 
+# Host-side sanitizers (AddressSanitizer + UndefinedBehaviorSanitizer) for
+# the C ABI's host code in api.hip; each flag applies to the host pass only.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+SAN_LIB_PATH = os.path.join(BUILD_DIR, "san", "libpowersort_hip_san.so")
+
+
+def build_host_sanitized() -> str:
+    """A copy of the library whose api.hip host code (argument checks,
+    workspace layout, pool, status strings) is built with AddressSanitizer
+    and UndefinedBehaviorSanitizer, linked with the regular objects of the
+    other sources (built by build() first).  Load it with clang's ASan
+    runtime preloaded (asan_runtime()) and POWERSORT_HIP_LIB pointing at it."""
+    objs = [os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o") for src in SOURCES if src != "api.hip"]
+    if not all(os.path.exists(o) for o in objs):
+        build()
+    os.makedirs(os.path.dirname(SAN_LIB_PATH), exist_ok=True)
+    api_o = os.path.join(os.path.dirname(SAN_LIB_PATH), "api_san.o")
+    flags = [f for f in CFLAGS if f != "-O3"] + ["-O1"]
+    r = subprocess.run([HIPCC, *flags, *HOST_SANITIZE, "-c", os.path.join(CSRC, "api.hip"), "-o", api_o],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the sanitized api.hip:\n{r.stderr}")
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan", *HOST_SANITIZE,
+                        "-o", SAN_LIB_PATH, api_o, *objs], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link of the sanitized library failed:\n{r.stderr}")
+    return SAN_LIB_PATH
+
+
+def asan_runtime() -> str:
+    """clang's shared AddressSanitizer runtime (for LD_PRELOAD)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("clang's libclang_rt.asan-x86_64.so not found under /opt/rocm/llvm")
+    return hits[-1]
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)

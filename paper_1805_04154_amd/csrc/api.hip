@@ -1,5 +1,6 @@
 // C ABI of the powersort library: argument checks, workspace layout, the
 // per-stream scratch pool and the launch sequence.
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -257,6 +258,7 @@ struct PoolEntry {
 };
 static std::mutex g_pool_mu;
 static std::unordered_map<void*, PoolEntry> g_pool;  // keyed by stream
+static uint64_t g_pool_limit = 0;                    // bytes per pool entry; 0 = no limit
 static thread_local std::string g_last_error;
 
 static ps_status fail(ps_status s, const std::string& msg) {
@@ -274,10 +276,14 @@ static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* o
         *out = opt->workspace;
         return PS_OK;
     }
+    const size_t want = bytes + bytes / 8;  // headroom against regrowth
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_limit && bytes > g_pool_limit)
+        return fail(PS_ERR_OUT_OF_MEMORY, "scratch of " + std::to_string(bytes) + " bytes exceeds the pool limit of " +
+                                              std::to_string(g_pool_limit) + " bytes (ps_set_pool_limit)");
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_pool_mu);
     PoolEntry& p = g_pool[(void*)st];
     if (p.ptr && p.bytes >= bytes && p.device == dev) {
         *out = p.ptr;
@@ -292,15 +298,15 @@ static ps_status get_workspace(hipStream_t st, size_t bytes, const ps_options* o
         p.bytes = 0;
         if (e != hipSuccess) return hip_fail(e, "hipFree");
     }
-    const size_t want = bytes + bytes / 8;  // headroom against regrowth
+    const size_t size = (g_pool_limit && want > g_pool_limit) ? bytes : want;
     void* ptr = nullptr;
-    e = hipMalloc(&ptr, want);
+    e = hipMalloc(&ptr, size);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        return fail(PS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        return fail(PS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(size) + " bytes failed");
     }
     p.ptr = ptr;
-    p.bytes = want;
+    p.bytes = size;
     p.device = dev;
     *out = ptr;
     return PS_OK;
@@ -881,17 +887,26 @@ static ps_status alphabetic_tree(const uint32_t* w, uint64_t r, uint8_t* powers,
 
 using namespace ps;
 
+// A C caller may pass any int as a ps_key_type: read the argument's bytes as
+// an int (a value outside the enumerators is not a valid value of the enum
+// in C++); check_common then rejects unknown types.
+static inline int key_int(const ps_key_type* t) {
+    int v;
+    memcpy(&v, t, sizeof v);
+    return v;
+}
+
 extern "C" {
 
 size_t ps_workspace_bytes(uint64_t n_total, uint64_t num_segments, ps_key_type key_type, int has_payload,
                           const ps_options* opt) {
     CallOpts o;
-    if (check_common((int)key_type, opt, &o) != PS_OK) return 0;
+    if (check_common(key_int(&key_type), opt, &o) != PS_OK) return 0;
     if (n_total > kMaxBatch || num_segments == 0 || num_segments >= kMaxTotal) return 0;
     if (num_segments == 1 && n_total > kMaxSegment) return 0;
     // above kMaxTotal the batch runs in chunks of at most kMaxTotal elements
     // (ps_segmented_sort), each needing no more than this
-    return make_layout(std::min(n_total, kMaxTotal), num_segments, key_bytes((int)key_type), has_payload != 0, o.w,
+    return make_layout(std::min(n_total, kMaxTotal), num_segments, key_bytes(key_int(&key_type)), has_payload != 0, o.w,
                        true, o.peek, o.nbuf)
         .total;
 }
@@ -909,7 +924,7 @@ ps_status ps_alphabetic_tree(const uint32_t* d_weights, uint64_t num_leaves, uin
 
 ps_status ps_sort(void* keys, uint32_t* payload, uint64_t n, ps_key_type key_type, const ps_options* opt,
                   uint64_t* d_merge_cost, void* stream) {
-    Call c{keys, payload, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
+    Call c{keys, payload, nullptr, 1, n, key_int(&key_type), 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
     return dispatch(c, opt, stream);
 }
 
@@ -917,7 +932,7 @@ ps_status ps_sort_no_alloc(void* keys, uint32_t* payload, uint64_t n, ps_key_typ
                            uint64_t* d_merge_cost, void* stream) {
     g_last_error.clear();
     CallOpts o;
-    ps_status s = check_common((int)key_type, opt, &o);
+    ps_status s = check_common(key_int(&key_type), opt, &o);
     if (s != PS_OK) return s;
     if (opt && opt->workspace)
         return fail(PS_ERR_INVALID_ARG, "ps_sort_no_alloc runs in the library's fixed scratch: "
@@ -925,7 +940,7 @@ ps_status ps_sort_no_alloc(void* keys, uint32_t* payload, uint64_t n, ps_key_typ
     if (n > kMaxSegment) return fail(PS_ERR_TOO_LARGE, "n must be below 2^31");
     if (n > 0 && !keys) return fail(PS_ERR_INVALID_ARG, "keys is NULL");
     const size_t need =
-        make_layout(n, 1, key_bytes((int)key_type), payload != nullptr, o.w, true, o.peek, o.nbuf).total;
+        make_layout(n, 1, key_bytes(key_int(&key_type)), payload != nullptr, o.w, true, o.peek, o.nbuf).total;
     if (need > kFixedScratchBytes)
         return fail(PS_ERR_TOO_LARGE, "this sort needs " + std::to_string(need) +
                                           " bytes of scratch; the fixed scratch holds " +
@@ -937,7 +952,7 @@ ps_status ps_sort_no_alloc(void* keys, uint32_t* payload, uint64_t n, ps_key_typ
     fixed.struct_size = sizeof(ps_options);
     fixed.workspace = ptr;
     fixed.workspace_bytes = kFixedScratchBytes;
-    Call c{keys, payload, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
+    Call c{keys, payload, nullptr, 1, n, key_int(&key_type), 0, d_merge_cost, nullptr, nullptr, Mode::Sort};
     c.prof = false;
     return dispatch(c, &fixed, stream);
 }
@@ -946,7 +961,7 @@ ps_status ps_segmented_sort(void* keys, uint32_t* payload, const uint64_t* d_off
                             uint64_t n_total, ps_key_type key_type, const ps_options* opt, uint64_t* d_merge_costs,
                             int32_t* d_status, void* stream) {
     if (!d_offsets) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
-    Call c{keys, payload, d_offsets, num_segments, n_total, (int)key_type, 0, d_merge_costs, d_status, nullptr,
+    Call c{keys, payload, d_offsets, num_segments, n_total, key_int(&key_type), 0, d_merge_costs, d_status, nullptr,
            Mode::Sort};
     return dispatch(c, opt, stream);
 }
@@ -954,7 +969,7 @@ ps_status ps_segmented_sort(void* keys, uint32_t* payload, const uint64_t* d_off
 ps_status ps_merge_cost(const void* keys, uint64_t n, ps_key_type key_type, const ps_options* opt,
                         uint64_t* d_merge_cost, void* stream) {
     if (!d_merge_cost) return fail(PS_ERR_INVALID_ARG, "d_merge_cost is NULL");
-    Call c{(void*)keys, nullptr, nullptr, 1, n, (int)key_type, 0, d_merge_cost, nullptr, nullptr, Mode::Cost};
+    Call c{(void*)keys, nullptr, nullptr, 1, n, key_int(&key_type), 0, d_merge_cost, nullptr, nullptr, Mode::Cost};
     return dispatch(c, opt, stream);
 }
 
@@ -963,7 +978,7 @@ ps_status ps_segmented_merge_cost(const void* keys, const uint64_t* d_offsets, u
                                   uint64_t* d_merge_costs, int32_t* d_status, void* stream) {
     if (!d_offsets) return fail(PS_ERR_INVALID_ARG, "d_offsets is NULL");
     if (!d_merge_costs) return fail(PS_ERR_INVALID_ARG, "d_merge_costs is NULL");
-    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, d_merge_costs, d_status,
+    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, key_int(&key_type), 0, d_merge_costs, d_status,
            nullptr, Mode::Cost};
     return dispatch(c, opt, stream);
 }
@@ -971,7 +986,7 @@ ps_status ps_segmented_merge_cost(const void* keys, const uint64_t* d_offsets, u
 ps_status ps_inspect(const void* keys, const uint64_t* d_offsets, uint64_t num_segments, uint64_t n_total,
                      ps_key_type key_type, const ps_options* opt, ps_inspect_out* out, void* stream) {
     if (!out) return fail(PS_ERR_INVALID_ARG, "out is NULL");
-    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, (int)key_type, 0, nullptr, nullptr, out,
+    Call c{(void*)keys, nullptr, d_offsets, num_segments, n_total, key_int(&key_type), 0, nullptr, nullptr, out,
            Mode::Inspect};
     return dispatch(c, opt, stream);
 }
@@ -1064,6 +1079,13 @@ ps_status ps_profile_read(ps_profile* out, int reset) {
     return PS_OK;
 }
 
+ps_status ps_set_pool_limit(uint64_t bytes) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool_limit = bytes;
+    return PS_OK;
+}
+
 ps_status ps_release(void* stream) {
     g_last_error.clear();
     std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -1080,7 +1102,12 @@ ps_status ps_release(void* stream) {
 }
 
 const char* ps_status_string(ps_status status) {
-    switch (status) {
+    // A C caller may pass any int: read the argument's bytes as an int, not
+    // as the enum (a value outside the enumerators is not a valid enum value
+    // in C++).
+    int code;
+    memcpy(&code, &status, sizeof code);
+    switch (code) {
     case PS_OK: return "PS_OK";
     case PS_ERR_INVALID_ARG: return "PS_ERR_INVALID_ARG: invalid argument";
     case PS_ERR_TOO_LARGE: return "PS_ERR_TOO_LARGE: input exceeds the supported size";

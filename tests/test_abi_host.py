@@ -188,3 +188,19 @@ def test_binding_rejects_mismatched_tensors():
         binding.segmented_sort(k, torch.zeros(10, dtype=torch.int32), off,
                                merge_costs=torch.zeros(2, dtype=torch.int64),
                                status=torch.zeros(1, dtype=torch.int32))
+
+
+def test_pool_limit_reports_out_of_memory_before_launch(lib):
+    """A call whose scratch exceeds the pool limit fails with
+    PS_ERR_OUT_OF_MEMORY before touching a device or enqueuing anything."""
+    fake = ctypes.c_void_p(0x1000)
+    need = lib.ps_workspace_bytes(1 << 20, 1, 0, 1, None)
+    try:
+        assert lib.ps_set_pool_limit(need - 1) == 0
+        assert lib.ps_sort(fake, fake, 1 << 20, 0, None, None, None) == -3
+        assert b"pool limit" in lib.ps_last_error()
+        off = ctypes.c_void_p(0x2000)
+        assert lib.ps_segmented_sort(fake, fake, off, 3, 1 << 20, 0, None, None, None, None) == -3
+        assert lib.ps_merge_cost(fake, 1 << 26, 0, None, fake, None) == -3  # metadata alone
+    finally:
+        lib.ps_set_pool_limit(0)

@@ -238,3 +238,30 @@ def test_runs_at_tile_boundaries(ps, w):
             check_sort(ps, v.astype(np.int32), w)
         except AssertionError as e:
             raise AssertionError(f"case {name} w {w}: {e}")
+
+
+def test_pool_limit_fails_with_nothing_enqueued():
+    """With the library's pool capped below what a sort needs, the call
+    raises PS_ERR_OUT_OF_MEMORY and leaves the keys untouched; without the
+    cap the same call sorts."""
+    import torch
+    from paper_1805_04154_amd import binding
+    binding.load_library()
+    wl = W.runs_2p20(n=1 << 20)
+    k, p = to_dev(wl.keys), to_dev(wl.payload)
+    s = torch.cuda.Stream()  # a stream without a pool entry yet
+    need = binding.workspace_bytes(wl.n, 1, torch.int32, True)
+    try:
+        binding.set_pool_limit(need - 1)
+        with pytest.raises(binding.PowersortError) as e:
+            binding.sort(k, p, stream=s)
+        assert e.value.status == -3
+    finally:
+        binding.set_pool_limit(0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(k, np.int32), wl.keys)
+    assert np.array_equal(to_host(p, np.uint32), wl.payload)
+    binding.sort(k, p, stream=s)
+    s.synchronize()
+    assert bool((k[1:] >= k[:-1]).all())
+    binding.release(s)
