@@ -83,13 +83,15 @@ TRACE_MD = os.path.join(ROOT, "profiles", "kernels_zipf_2p28_i32.md")
 
 
 def merge_kernel_digest() -> str:
-    """Digest of the merge-pass kernel's source text (its LDS struct and body)."""
+    """Digest of the merge-pass kernels' source text (their LDS layout and
+    bodies: the two-input and the four-input merge)."""
     src = open(os.path.join(ROOT, "paper_1805_04154_amd", "csrc", "merge.hip")).read()
-    a = src.index("template <int KT, int TILE>\nstruct MergeShared")
-    a2 = src.index("\n};\n", a)
-    b = src.index("template <int KT, bool HP, int NT, int IT>\n__global__ __launch_bounds__(NT) void merge_pass_kernel")
-    b2 = src.index("\n}\n", b)
-    return hashlib.sha256((src[a:a2] + src[b:b2]).encode()).hexdigest()[:16]
+    parts = []
+    for start in ("__device__ __forceinline__ uint32_t lpad(", "void merge_quad_kernel(MoveArgs a, uint32_t p) {",
+                  "void merge_pass_kernel(MoveArgs a, uint32_t p) {"):
+        a = src.index(start)
+        parts.append(src[a:src.index("\n}\n", a)])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def profile_fields(path: str) -> dict:

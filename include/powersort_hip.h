@@ -209,9 +209,13 @@ ps_status ps_sort_no_alloc(void *keys, uint32_t *payload, uint64_t n, ps_key_typ
 /* Launch shape of the data-movement kernels (process-wide).  Every value
  * changes only speed, never results: grids are workgroup counts of
  * grid-stride kernels; merge_tile is the outputs per merge-path tile, 2048,
- * 4096 or 8192 (8192 applies to 4-byte keys; 8-byte keys then use 4096).
- * Defaults: merge_tile 8192, grid_merge 2048, grid_split 512, grid_fused
- * 2048, grid_big_leaf 2048.
+ * 4096 or 8192 (8192 applies to 4-byte keys; 8-byte keys then use 4096);
+ * merge_levels is the number of tree levels one merge pass does, 1 or 2:
+ * with 2 (4-byte keys only) a node of more than 4096 elements at odd depth
+ * in the merge tree is not written out but merged in the same pass as its
+ * parent, which then merges up to four inputs.
+ * Defaults: merge_tile 8192, merge_levels 1, grid_merge 2048, grid_split
+ * 512, grid_fused 2048, grid_big_leaf 2048.
  * Zero fields keep their current value.  Written by the project's
  * autotuner for a workload; read back with ps_get_tuning. */
 typedef struct {
@@ -221,10 +225,11 @@ typedef struct {
     uint32_t grid_merge;
     uint32_t grid_split;
     uint32_t merge_tile;
+    uint32_t merge_levels;
 } ps_tuning;
 
 /* Set (tuning != NULL) or reset to defaults (NULL) the launch shape.
- * Returns PS_ERR_INVALID_ARG for a bad struct_size or merge_tile, and
+ * Returns PS_ERR_INVALID_ARG for a bad struct_size, merge_tile or merge_levels, and
  * PS_ERR_UNSUPPORTED for a grid above 65536. */
 ps_status ps_set_tuning(const ps_tuning *tuning);
 

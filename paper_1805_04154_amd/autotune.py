@@ -1,7 +1,9 @@
 """Autotuner for the launch shape of the data-movement kernels.
 
-The tunables (``ps_tuning``) change speed only, never results: the grid sizes
-of the grid-stride kernels and the merge-path tile (2048, 4096 or 8192 outputs).
+The tunables (``ps_tuning``) change speed only, never results: the number of
+merge-tree levels one merge pass does (1, or 2 with absorbed children), the
+grid sizes of the grid-stride kernels and the merge-path tile (2048, 4096 or
+8192 outputs).
 ``tune()`` times every candidate on a caller-supplied step (which must
 restore its own input before sorting), keeps the fastest, and records it in a
 JSON cache keyed by a workload signature so later runs start from the tuned
@@ -25,14 +27,17 @@ SHIPPED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 
 def candidates(small: bool = False) -> list[dict]:
-    """The search space: merge tile x merge grid x fused grid x split grid."""
+    """The search space: tree levels per merge pass (1, or 2 with absorbed
+    children) x merge tile x merge grid x fused grid x split grid."""
+    levels = (1, 2)
     tiles = (8192, 4096, 2048)
     merge_grids = (1024, 2048, 4096) if not small else (2048,)
     fused_grids = (1024, 2048) if not small else (2048,)
     split_grids = (256, 512, 1024) if not small else (512,)
     out = []
-    for t, gm, gf, gs in itertools.product(tiles, merge_grids, fused_grids, split_grids):
-        out.append({"merge_tile": t, "grid_merge": gm, "grid_fused": gf, "grid_split": gs, "grid_big_leaf": 2048})
+    for lv, t, gm, gf, gs in itertools.product(levels, tiles, merge_grids, fused_grids, split_grids):
+        out.append({"merge_levels": lv, "merge_tile": t, "grid_merge": gm, "grid_fused": gf, "grid_split": gs,
+                    "grid_big_leaf": 2048})
     return out
 
 

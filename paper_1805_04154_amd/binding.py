@@ -28,7 +28,7 @@ EXPORTS = ("ps_workspace_bytes", "ps_sort", "ps_sort_no_alloc", "ps_segmented_so
            "ps_inspect", "ps_alphabetic_tree", "ps_set_tuning", "ps_get_tuning", "ps_profile_enable",
            "ps_profile_read", "ps_set_pool_limit", "ps_release",
            "ps_status_string", "ps_last_error")
-TUNING_FIELDS = ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split", "merge_tile")
+TUNING_FIELDS = ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split", "merge_tile", "merge_levels")
 PROF_GROUPS = ("partition", "tree", "lists", "big_leaf", "fused", "merge", "split")
 
 
@@ -43,9 +43,7 @@ class PsInspectOut(ctypes.Structure):
 
 
 class PsTuning(ctypes.Structure):
-    _fields_ = [("struct_size", ctypes.c_uint32)] + [(f, ctypes.c_uint32) for f in
-                                                     ("grid_big_leaf", "grid_fused", "grid_merge", "grid_split",
-                                                      "merge_tile")]
+    _fields_ = [("struct_size", ctypes.c_uint32)] + [(f, ctypes.c_uint32) for f in TUNING_FIELDS]
 
 
 class PsProfile(ctypes.Structure):

@@ -163,7 +163,8 @@ struct Layout {
     uint32_t ntab[4];
     int levels;
     size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt, nsize;
-    size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split;
+    size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split, span;
+    size_t child_l, child_r;
     uint32_t rmax;
     uint64_t split_cap = 0;
     size_t peek_f[2] = {0, 0};  // peeksort frontiers (ranges of one depth)
@@ -230,14 +231,25 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
         L.node_rec = take(at, r1 * sizeof(NodeRec));
         L.bucket_tile = take(at, r1 * 4);
         L.leaf_tile = take(at, r1 * 4);
-        // merge tiles over all passes: sum of big-node sizes / tile + nodes,
-        // with the sum bounded by M <= n (lg n + 2) (Thm. "powersort")
+        L.child_l = take(at, r1 * 4);
+        L.child_r = take(at, r1 * 4);
+        // Merge tiles over all passes: at most (merged elements) / (half the
+        // smallest tile, the splitter spacing of two-level merges) + one per
+        // merged node, and every merged node holds more than kFuse elements.
+        // The merged elements are at most n per pass (a pass's nodes are
+        // disjoint) and at most M <= n (lg n + 2) in all (Thm. "powersort");
+        // a powersort merges in at most pfuse passes (see run()).
         const uint64_t lg = 64 - __builtin_clzll(N | 1);
-        L.split_cap = (N * (lg + 2)) / kMergeTileMin + r1 + 64;
+        uint64_t pfuse = 1;
+        while (((uint64_t)kFuse << pfuse) < 3 * N) ++pfuse;
+        const uint64_t merged = N * (peek ? lg + 2 : std::min<uint64_t>(lg + 2, pfuse));
+        L.split_cap = merged / kQuadSpacing + merged / kFuse + 64;
         L.split = take(at, L.split_cap * sizeof(SplitRec));
+        L.span = take(at, L.split_cap * sizeof(TileSpan));
     } else {
         L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.biglist = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
-        L.split = 0;
+        L.child_l = L.child_r = 0;
+        L.split = L.span = 0;
     }
     if (peek) {
         // ranges of one depth are disjoint and hold >= 2 leaves each
@@ -590,7 +602,12 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ta.lists.node_rec = (NodeRec*)at(L.node_rec);
         ta.lists.bucket_tile = (uint32_t*)at(L.bucket_tile);
         ta.lists.leaf_tile = (uint32_t*)at(L.leaf_tile);
+        ta.lists.child_l = (uint32_t*)at(L.child_l);
+        ta.lists.child_r = (uint32_t*)at(L.child_r);
         ta.lists.nbuf = c.nbuf;
+        // two-level passes need the split pass's records (4-byte keys);
+        // 8-byte keys merge one level per pass with in-kernel co-ranks
+        ta.lists.levels = kb == 4 ? tune.merge_levels : 1u;
         if (c.prof && prof_on()) {
             std::lock_guard<std::mutex> lk(g_prof_mu);
             ta.prof = g_prof.dev;
@@ -624,9 +641,11 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.bucket_tile = ta.lists.bucket_tile;
         ma.leaf_tile = ta.lists.leaf_tile;
         ma.split = (SplitRec*)at(L.split);
+        ma.span = (TileSpan*)at(L.span);
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
         ma.fuse_max_leaves = fuse_max_leaves(c.w);
         ma.merge_tile = merge_tile;
+        ma.n = N;
         // Powers: by the definition of a node power, P_j <= ceil(lg(2n / (L_{j-1}
         // + L_j))), and two adjacent leaves of a segment hold at least w + 1
         // elements (only a segment's last leaf may be shorter than w), so no
@@ -661,6 +680,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
             // them inside the merge pass
             if (kb == 4) e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);
             if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);
+            if (e == hipSuccess && ta.lists.levels == 2) e = stage(PS_PROF_MERGE, 6, p, tune.grid_merge);
         }
         if (e != hipSuccess) return hip_fail(e, "merge launch");
         if (c.prof && prof_on()) {
@@ -1001,6 +1021,7 @@ ps_status ps_set_tuning(const ps_tuning* t) {
     if (t->struct_size != sizeof(ps_tuning)) return fail(PS_ERR_INVALID_ARG, "ps_tuning.struct_size mismatch");
     if (t->merge_tile && t->merge_tile != 2048 && t->merge_tile != 4096 && t->merge_tile != 8192)
         return fail(PS_ERR_INVALID_ARG, "merge_tile must be 2048, 4096 or 8192");
+    if (t->merge_levels > 2) return fail(PS_ERR_INVALID_ARG, "merge_levels must be 1 or 2");
     const uint32_t grids[4] = {t->grid_big_leaf, t->grid_fused, t->grid_merge, t->grid_split};
     for (uint32_t g : grids)
         if (g > 65536) return fail(PS_ERR_UNSUPPORTED, "grid above 65536");
@@ -1010,6 +1031,7 @@ ps_status ps_set_tuning(const ps_tuning* t) {
     if (t->grid_merge) n.grid_merge = t->grid_merge;
     if (t->grid_split) n.grid_split = t->grid_split;
     if (t->merge_tile) n.merge_tile = t->merge_tile;
+    if (t->merge_levels) n.merge_levels = t->merge_levels;
     g_tune = n;
     return PS_OK;
 }
@@ -1023,6 +1045,7 @@ ps_status ps_get_tuning(ps_tuning* out) {
     out->grid_merge = g_tune.grid_merge;
     out->grid_split = g_tune.grid_split;
     out->merge_tile = g_tune.merge_tile;
+    out->merge_levels = g_tune.merge_levels;
     return PS_OK;
 }
 

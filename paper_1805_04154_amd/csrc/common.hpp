@@ -86,6 +86,11 @@ __host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFus
 // either.
 constexpr uint32_t kMergeTileDefault = 8192;
 constexpr uint32_t kMergeTileMin = 2048;
+// Merges with absorbed children: splitters every kQuadSpacing positions of
+// each child's merge, so a tile holds at most 2 kQuadSpacing outputs, and
+// the merge pass packs consecutive tiles into groups of up to kQuadTile.
+constexpr uint32_t kQuadSpacing = 1024;
+constexpr uint32_t kQuadTile = 4096;
 
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;
@@ -100,11 +105,19 @@ constexpr int kLeafTile = 16384;
 //    writes 0: such a leaf is copied to 2 like the root's other children.
 //    This saves the copy of every long leaf at odd depth for one more
 //    array of scratch.
-__host__ __device__ constexpr uint32_t node_buf(uint32_t depth, uint32_t nbuf) {
-    return nbuf == 3 ? (depth == 0 ? 0u : 1u + (depth & 1u)) : (depth & 1u);
+//  * Two-level passes (a big node at odd depth merged together with its
+//    parent, never written out): the same rules by "pass level"
+//    (depth + 1) / 2 in place of the depth, so that every input of a merge
+//    -- a child, or a grandchild through an absorbed child, all at the same
+//    pass level -- sits in an array other than the merge's own.
+__host__ __device__ constexpr uint32_t pass_level(uint32_t depth, uint32_t levels) {
+    return levels == 2 ? (depth + 1) >> 1 : depth;
 }
-__host__ __device__ constexpr uint32_t big_leaf_buf(uint32_t depth, uint32_t nbuf) {
-    return nbuf == 3 ? (depth == 1 ? 2u : 0u) : (depth & 1u);
+__host__ __device__ constexpr uint32_t node_buf(uint32_t level, uint32_t nbuf) {
+    return nbuf == 3 ? (level == 0 ? 0u : 1u + (level & 1u)) : (level & 1u);
+}
+__host__ __device__ constexpr uint32_t big_leaf_buf(uint32_t level, uint32_t nbuf) {
+    return nbuf == 3 ? (level == 1 ? 2u : 0u) : (level & 1u);
 }
 // The array a long leaf is copied into when it moves.
 __host__ __device__ constexpr uint32_t leaf_copy_buf(uint32_t nbuf) { return nbuf == 3 ? 2u : 1u; }

@@ -15,20 +15,45 @@ struct Counters {
     uint32_t ptiles[kMaxPass + 1];  // merge tiles per pass; [0] = big-leaf tiles
     uint32_t sbase[kMaxPass + 1];   // first split record of each pass
     uint32_t peek_count[kMaxPass + 1];  // peeksort: ranges of each depth
+    uint32_t pcount_q[kMaxPass + 1];    // nodes per pass with an absorbed child (last in their bucket)
+    uint32_t pqfill[kMaxPass + 1];
+    uint32_t ptq[kMaxPass + 1];         // first tile of those nodes within the pass
 };
 
 struct Mask2 {
     uint64_t a, b;
 };
 
+// A merge of a pass: node X = [lo, hi) with children [lo, mid) and [mid, hi).
+// When a child is absorbed (two-level passes: a big child at odd depth is
+// merged in the same pass as its parent, never written out), its own
+// children are inputs: the left child [lo, mid) is the merge of runs
+// A = [lo, m1) and B = [m1, mid), the right child of C = [mid, m2) and
+// D = [m2, hi).  A child that is an input has m1 = mid (B empty) or m2 = hi
+// (D empty).  The result is the stable merge of A, B, C, D in that priority
+// on equal keys.
 struct NodeRec {
-    uint32_t lo, mid, hi;  // a merge of [lo, mid) and [mid, hi)
-    uint32_t bufs;         // arrays: result (bits 0-1), left child (2-3), right child (4-5)
+    uint32_t lo, m1, mid, m2, hi;
+    uint32_t bufs;  // arrays: result (bits 0-1), A (2-3), B (4-5), C (6-7), D (8-9)
 };
+__host__ __device__ constexpr bool node_is_quad(const NodeRec& R) { return R.m1 != R.mid || R.m2 != R.hi; }
+// A merge tile of a pass, written by the split pass: its part of each input
+// run A, B, C, D as element positions [s, e) in the run's array, where its
+// output starts, and the arrays (as NodeRec.bufs).
 struct SplitRec {
-    uint32_t node;    // bucket entry of the tile's node
-    uint32_t corank;  // A elements before the tile's first output
+    uint32_t s[4];
+    uint32_t e[4];
+    uint32_t out;
+    uint32_t bufs;
 };
+// Per merge tile, for packing consecutive tiles: the result positions of
+// its first output (bit 31: the tile is its node's first) and one past its
+// last.
+struct TileSpan {
+    uint32_t start;
+    uint32_t end;
+};
+constexpr uint32_t kFirstTile = 0x80000000u;
 struct UnitRec {
     uint32_t ua, ub, lo, hi;  // leaves [ua, ub) spanning elements [lo, hi)
 };
@@ -38,12 +63,15 @@ struct TreeLists {
     uint8_t* unit_par;
     uint32_t* bigleaf;
     uint8_t* bigleaf_mode;
-    uint32_t* biglist;      // big nodes in discovery order
+    uint32_t* biglist;      // big nodes in discovery order; bit 31: the node absorbs a child
     uint32_t* bucket;       // big nodes grouped by power
     NodeRec* node_rec;      // merge record of each bucket entry
     uint32_t* bucket_tile;  // first merge tile of each bucket entry (within its pass)
     uint32_t* leaf_tile;    // first copy tile of each big leaf
+    uint32_t* child_l;      // left child node of node j (when its left part has >= 2 leaves)
+    uint32_t* child_r;      // right child node of node j (when its right part has >= 2 leaves)
     uint32_t nbuf;          // 2 or 3 data arrays (node_buf / big_leaf_buf)
+    uint32_t levels;        // tree levels merged per pass: 1, or 2 (big nodes at odd depth absorbed)
 };
 
 struct TreeArgs {
@@ -122,10 +150,12 @@ struct MoveArgs {
     const uint32_t* bucket_tile;
     const uint32_t* leaf_tile;
     SplitRec* split;
+    TileSpan* span;            // split_cap entries, beside split
     uint32_t split_cap;        // capacity of split (records)
     uint32_t fuse_max_leaves;  // leaves a fused subtree can hold at this w
     uint32_t merge_tile;       // outputs per merge-path tile
     uint32_t leaf_copy;        // array that copied long leaves go to (leaf_copy_buf)
+    uint32_t n;                // elements of the call
 };
 
 // Launch shape chosen by the caller (ps_set_tuning) or the defaults.
@@ -135,6 +165,7 @@ struct Tuning {
     uint32_t grid_merge = 2048;
     uint32_t grid_split = 512;
     uint32_t merge_tile = kMergeTileDefault;
+    uint32_t merge_levels = 1;  // 1: one tree level per pass; 2: two-level passes (4-byte keys)
 };
 
 enum : uint8_t { kLeafNoop = 0, kLeafCopy = 1, kLeafRevCopy = 2, kLeafRevInPlace = 3 };

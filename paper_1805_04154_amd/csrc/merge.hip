@@ -595,34 +595,158 @@ struct MergeShared {
     U sk[TILE];
     uint32_t sp[TILE];
 };
+// LDS of the 4-byte-key merge passes: one pad word after every eight, so
+// that a thread writing its eight consecutive merge outputs (lane L at
+// 8 L + i) hits a different bank from every other lane (9 L + i).
+__device__ __forceinline__ uint32_t lpad(uint32_t x) { return x + (x >> 3); }
+template <int KT, int TILE>
+struct MergeSharedPad {
+    using U = typename Key<KT>::ukey;
+    U sk[TILE + TILE / 8];
+    uint32_t sp[TILE + TILE / 8];
+};
 
-// Split pass: the merge-path co-rank at the start of every tile of pass p,
-// one thread per tile.  Co-rank of diagonal d in the stable merge of
-// A = [lo, mid) and B = [mid, hi): the number of A elements among the first d
-// outputs, A going first on equal keys, by binary search.  All tiles of the
-// pass search at once; their first levels share cache lines.
+// Key-order bounds in a sorted run: the number of run elements whose key is
+// below v (lower) or not above v (upper).
+template <int KT>
+__device__ __forceinline__ uint32_t lower_count(const typename Key<KT>::raw* __restrict__ x, uint32_t n,
+                                                typename Key<KT>::ukey v) {
+    uint32_t l = 0, h = n;
+    while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (Key<KT>::ord(x[m]) < v) l = m + 1; else h = m;
+    }
+    return l;
+}
+template <int KT>
+__device__ __forceinline__ uint32_t upper_count(const typename Key<KT>::raw* __restrict__ x, uint32_t n,
+                                                typename Key<KT>::ukey v) {
+    uint32_t l = 0, h = n;
+    while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (Key<KT>::ord(x[m]) <= v) l = m + 1; else h = m;
+    }
+    return l;
+}
+// Co-rank of diagonal d in the stable merge of sorted runs x (first on equal
+// keys) and y: the number of x elements among the first d outputs.
+template <int KT>
+__device__ __forceinline__ uint32_t corank(const typename Key<KT>::raw* __restrict__ x, uint32_t nx,
+                                           const typename Key<KT>::raw* __restrict__ y, uint32_t ny, uint32_t d) {
+    uint32_t l = d > ny ? d - ny : 0, h = min(d, nx);
+    while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (Key<KT>::ord(x[m]) <= Key<KT>::ord(y[d - 1 - m])) l = m + 1; else h = m;
+    }
+    return l;
+}
+
+// Split pass: where every merge tile of pass p starts, one thread per tile.
+//  * A node with two inputs A = [lo, mid) and C = [mid, hi) has tiles of
+//    merge_tile outputs: the tile starting at output d takes the co-rank of
+//    diagonal d (A elements among the first d outputs, A first on equal keys).
+//  * A node with an absorbed child merges the left child L = A + B with the
+//    right child R = C + D, neither written out.  Its tile starts are the
+//    node's start and "splitters" every g = kQuadSpacing positions along L
+//    and along R: splitter i of L is its element L[i] (found by the co-rank
+//    of i in A, B), and it starts where the R elements below its key end
+//    (L goes first on equal keys); splitter j of R is R[j], preceded by the
+//    L elements not above its key.  Consecutive starts are at most g apart
+//    in L and in R, so a tile holds at most 2g outputs (the merge pass packs
+//    consecutive tiles into groups of up to kQuadTile).  Their
+//    order in the result has a closed form: R's splitter m g precedes L's
+//    element L[i] exactly when m g < (R elements before L[i]), and vice
+//    versa, so each splitter's tile index is its own index plus the number
+//    of the other child's splitters before it.
+// All tiles of the pass search at once; their first levels share cache lines.
+// Each boundary writes the start of its tile and the end of the previous
+// one (the last boundary of a node also ends its tile at the node's end), so
+// a merge tile is read as one record.
 template <int KT>
 __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p) {
     using K = Key<KT>;
     using raw = typename K::raw;
+    using U = typename K::ukey;
     const uint32_t ntiles = a.cnt->ptiles[p];
     const uint32_t nb = a.cnt->pcount[p];
     const uint32_t bbase = a.cnt->pbase[p];
     const uint32_t sb = a.cnt->sbase[p];
     if (nb == 0) return;
+    const uint32_t g = kQuadSpacing;
     for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
         const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
-        const NodeRec R = a.node_rec[bbase + k];
+        const uint32_t node = bbase + k;
+        const NodeRec R = a.node_rec[node];
+        const uint32_t first = a.bucket_tile[node];
+        const uint32_t u = t - first;
         const raw* A = (const raw*)pick3(a.keys, (R.bufs >> 2) & 3u) + R.lo;
-        const raw* B = (const raw*)pick3(a.keys, (R.bufs >> 4) & 3u) + R.mid;
-        const uint32_t la = R.mid - R.lo, lb = R.hi - R.mid;
-        const uint32_t d = (t - a.bucket_tile[bbase + k]) * a.merge_tile;
-        uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
-        while (l < h) {
-            const uint32_t m = (l + h) >> 1;
-            if (K::ord(A[m]) <= K::ord(B[d - 1 - m])) l = m + 1; else h = m;
+        const raw* B = (const raw*)pick3(a.keys, (R.bufs >> 4) & 3u) + R.m1;
+        const raw* C = (const raw*)pick3(a.keys, (R.bufs >> 6) & 3u) + R.mid;
+        const raw* D = (const raw*)pick3(a.keys, (R.bufs >> 8) & 3u) + R.m2;
+        const uint32_t na = R.m1 - R.lo, nbb = R.mid - R.m1, nc = R.m2 - R.mid, nd = R.hi - R.m2;
+        uint32_t idx = u, last;
+        uint32_t ca = 0, cb = 0, cc = 0, cd = 0;  // elements of A, B, C, D before the boundary
+        if (!node_is_quad(R)) {
+            last = (R.hi - R.lo - 1) / a.merge_tile;
+            const uint32_t d = u * a.merge_tile;
+            ca = corank<KT>(A, na, C, nc, d);
+            cc = d - ca;
+        } else {
+            const uint32_t nl = na + nbb, nr = nc + nd;
+            const uint32_t sl = (nl - 1) / g, sr = (nr - 1) / g;  // splitters of L and R
+            last = sl + sr;
+            if (u == 0) {
+                idx = 0;
+            } else if (u <= sl) {
+                const uint32_t i = u * g;
+                ca = nbb ? corank<KT>(A, na, B, nbb, i) : i;
+                cb = i - ca;
+                const bool from_a = cb >= nbb || (ca < na && K::ord(A[ca]) <= K::ord(B[cb]));
+                const U v = K::ord(from_a ? A[ca] : B[cb]);
+                cc = lower_count<KT>(C, nc, v);
+                cd = nd ? lower_count<KT>(D, nd, v) : 0u;
+                const uint32_t before = cc + cd;
+                idx = u + min(sr, before ? (before - 1) / g : 0u);
+            } else {
+                const uint32_t m = u - sl, j = m * g;
+                cc = nd ? corank<KT>(C, nc, D, nd, j) : j;
+                cd = j - cc;
+                const bool from_c = cd >= nd || (cc < nc && K::ord(C[cc]) <= K::ord(D[cd]));
+                const U v = K::ord(from_c ? C[cc] : D[cd]);
+                ca = upper_count<KT>(A, na, v);
+                cb = nbb ? upper_count<KT>(B, nbb, v) : 0u;
+                const uint32_t before = ca + cb;
+                idx = m + min(sl, before ? (before - 1) / g : 0u);
+            }
         }
-        if (sb + t < a.split_cap) a.split[sb + t] = SplitRec{bbase + k, l};
+        const uint32_t pa = R.lo + ca, pb = R.m1 + cb, pc = R.mid + cc, pd = R.m2 + cd;
+        const uint32_t out = R.lo + ca + cb + cc + cd;
+        const uint32_t at = sb + first + idx;
+        if (at < a.split_cap) {
+            SplitRec& r = a.split[at];
+            r.s[0] = pa;
+            r.s[1] = pb;
+            r.s[2] = pc;
+            r.s[3] = pd;
+            r.out = out;
+            r.bufs = R.bufs;
+            a.span[at].start = out | (idx == 0 ? kFirstTile : 0u);
+            if (idx == last) {
+                r.e[0] = R.m1;
+                r.e[1] = R.mid;
+                r.e[2] = R.m2;
+                r.e[3] = R.hi;
+                a.span[at].end = R.hi;
+            }
+        }
+        if (idx > 0 && at - 1 < a.split_cap) {
+            SplitRec& q = a.split[at - 1];
+            q.e[0] = pa;
+            q.e[1] = pb;
+            q.e[2] = pc;
+            q.e[3] = pd;
+            a.span[at - 1].end = out;
+        }
     }
 }
 
@@ -643,10 +767,10 @@ __device__ __forceinline__ void merge_tile(const MoveArgs& a, MergeShared<KT, NT
     const uint32_t lo = R.lo, mid = R.mid, hi = R.hi;
     const uint32_t bufs = R.bufs;
     const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + lo;
-    const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 4) & 3u) + mid;
+    const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 6) & 3u) + mid;  // the right input C
     raw* dst = (raw*)pick3u(a.keys, bufs & 3u);
     const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + lo;
-    const uint32_t* psrcB = pick3u(a.pay, (bufs >> 4) & 3u) + mid;
+    const uint32_t* psrcB = pick3u(a.pay, (bufs >> 6) & 3u) + mid;
     uint32_t* pdst = pick3u(a.pay, bufs & 3u);
     const uint32_t la = mid - lo, tot = hi - lo;
     const uint32_t k0 = tt * TILE, k1 = min(tot, k0 + TILE);
@@ -765,7 +889,7 @@ __global__ __launch_bounds__(NT) void merge_pass_cr_kernel(MoveArgs a, uint32_t 
             const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
             const NodeRec Rk = a.node_rec[bbase + k];
             const raw* A = (const raw*)pick3(a.keys, (Rk.bufs >> 2) & 3u) + Rk.lo;
-            const raw* B = (const raw*)pick3(a.keys, (Rk.bufs >> 4) & 3u) + Rk.mid;
+            const raw* B = (const raw*)pick3(a.keys, (Rk.bufs >> 6) & 3u) + Rk.mid;  // the right input C
             const uint32_t la = Rk.mid - Rk.lo, lb = Rk.hi - Rk.mid;
             const uint32_t d = (t - a.bucket_tile[bbase + k]) * TILE;
             uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
@@ -782,37 +906,248 @@ __global__ __launch_bounds__(NT) void merge_pass_cr_kernel(MoveArgs a, uint32_t 
     }
 }
 
-// NT threads x IT outputs per tile (the tile size a.merge_tile).
+// Merges of nodes with an absorbed child (the tail part of pass p's tiles),
+// NT threads x IT outputs per group of tiles.  A group reads its part of
+// each input run (A, B, C, D; B or D is empty when that child is an input)
+// into LDS, merges A with B and C with D (the absorbed children's parts),
+// then the two results, and writes its part of the node.
 template <int KT, bool HP, int NT, int IT>
-__global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void merge_quad_kernel(MoveArgs a, uint32_t p) {
     constexpr int TILE = NT * IT;
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
-    __shared__ MergeShared<KT, TILE> sm;
+    __shared__ MergeSharedPad<KT, TILE> sm;
     const uint32_t sb = a.cnt->sbase[p];
     // never read past the split records (the tile count is bounded by the
     // merge cost, so this only guards against inconsistent lists)
-    const uint32_t ntiles = min(a.cnt->ptiles[p], a.split_cap > sb + 1 ? a.split_cap - sb - 1 : 0u);
+    const uint32_t ntiles = min(a.cnt->ptiles[p], a.split_cap > sb ? a.split_cap - sb : 0u);
+    const uint32_t t0 = min(a.cnt->ptq[p], ntiles);
+    if (t0 >= ntiles) return;
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    // Every workgroup takes a contiguous chunk of these tiles and packs
+    // consecutive tiles of one node into groups of at most TILE outputs
+    // (their tiles hold at most 2 kQuadSpacing <= TILE).  Every wave finds
+    // the same group from the tile spans, so no barrier is needed to share
+    // it.
+    static_assert(2 * kQuadSpacing <= (uint32_t)TILE, "a tile of a node with absorbed children must fit");
+    const uint32_t chunk = (ntiles - t0 + gridDim.x - 1) / gridDim.x;
+    if (t0 + blockIdx.x * chunk >= ntiles) return;
+    const uint32_t tb = t0 + blockIdx.x * chunk, te = min(ntiles, tb + chunk);
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
+    // tiles in the group starting at t (at least one)
+    auto group_len = [&](uint32_t t) -> uint32_t {
+        const uint32_t q = t + lane;
+        const uint32_t base = uni(a.span[sb + t].start) & ~kFirstTile;
+        bool ok = false;
+        if (q < te) {
+            const TileSpan sq = a.span[sb + q];
+            ok = (lane == 0 || !(sq.start & kFirstTile)) && sq.end >= base && sq.end - base <= (uint32_t)TILE;
+        }
+        const uint64_t bad = __ballot(!ok);
+        const uint32_t g = bad ? (uint32_t)__ffsll((unsigned long long)bad) - 1u : 64u;
+        return uni(g > 0 ? g : 1u);
+    };
+    // The next group's length and records are fetched while the current
+    // group is merged (kept in scalar registers: they are block-uniform).
+    struct Group {
+        uint32_t s[4], e[4], out, bufs;
+    };
+    auto group_at = [&](uint32_t t, uint32_t len) -> Group {
+        const SplitRec& f = a.split[sb + t];
+        const SplitRec& l = a.split[sb + t + len - 1];
+        return Group{{uni(f.s[0]), uni(f.s[1]), uni(f.s[2]), uni(f.s[3])},
+                     {uni(l.e[0]), uni(l.e[1]), uni(l.e[2]), uni(l.e[3])},
+                     uni(f.out),
+                     uni(f.bufs)};
+    };
+    uint32_t t = tb, glen = group_len(tb);
+    Group cur = group_at(t, glen);
+    while (t < te) {
+        const uint32_t bufs = cur.bufs, out0 = cur.out;
+        const uint32_t sa = cur.s[0], sbp = cur.s[1], sc = cur.s[2], sd = cur.s[3];
+        const uint32_t ea = cur.e[0], eb = cur.e[1], ec = cur.e[2], ed = cur.e[3];
+        t += glen;
+        if (t < te) {
+            glen = group_len(t);
+            cur = group_at(t, glen);
+        }
+        // Consistent records have s <= e in every run, at most TILE outputs
+        // and positions below n; the checks only keep inconsistent lists
+        // inside the arrays and the tile.
+        const uint32_t na = ea > sa ? ea - sa : 0u, nbp = eb > sbp ? eb - sbp : 0u;
+        const uint32_t nc = ec > sc ? ec - sc : 0u, nd = ed > sd ? ed - sd : 0u;
+        const uint32_t nl = na + nbp, ncl = nl + nc, nt = ncl + nd;
+        if (nt > (uint32_t)TILE || max(max(ea, eb), max(ec, ed)) > a.n || out0 + nt > a.n) continue;
+        const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + sa;
+        const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 4) & 3u) + sbp;
+        const raw* srcC = (const raw*)pick3u(a.keys, (bufs >> 6) & 3u) + sc;
+        const raw* srcD = (const raw*)pick3u(a.keys, (bufs >> 8) & 3u) + sd;
+        const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + sa;
+        const uint32_t* psrcB = pick3u(a.pay, (bufs >> 4) & 3u) + sbp;
+        const uint32_t* psrcC = pick3u(a.pay, (bufs >> 6) & 3u) + sc;
+        const uint32_t* psrcD = pick3u(a.pay, (bufs >> 8) & 3u) + sd;
+        raw* dst = (raw*)pick3u(a.keys, bufs & 3u) + out0;
+        uint32_t* pdst = pick3u(a.pay, bufs & 3u) + out0;
+        U kr[IT];
+        uint32_t pr[IT];
+        {
+            raw kv[IT];
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = tid + i * NT;
+                // masked loads with scalar bases (not a per-lane pointer
+                // select, which costs 64-bit address arithmetic)
+                if (x < na) {
+                    kv[i] = srcA[x];
+                    if (HP) pr[i] = psrcA[x];
+                } else if (x < nl) {
+                    kv[i] = srcB[x - na];
+                    if (HP) pr[i] = psrcB[x - na];
+                } else if (x < ncl) {
+                    kv[i] = srcC[x - nl];
+                    if (HP) pr[i] = psrcC[x - nl];
+                } else if (x < nt) {
+                    kv[i] = srcD[x - ncl];
+                    if (HP) pr[i] = psrcD[x - ncl];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = tid + i * NT;
+                if (x < nt) {
+                    sm.sk[lpad(x)] = K::ord(kv[i]);
+                    if (HP) sm.sp[lpad(x)] = pr[i];
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t dx = tid * IT;
+        if (nbp | nd) {
+            // Absorbed children: merge sk[0, na) with sk[na, nl) (the left
+            // child's part) and sk[nl, ncl) with sk[ncl, nt) (the right
+            // child's), each stably, first run first on equal keys.
+            if (dx < nt) {
+                const bool right = dx >= nl;
+                const uint32_t base = right ? nl : 0u, n1 = right ? nc : na, n2 = right ? nd : nbp;
+                const uint32_t dg = dx - base;
+                uint32_t l = dg > n2 ? dg - n2 : 0, h = min(dg, n1);
+                while (l < h) {
+                    const uint32_t m = (l + h) >> 1;
+                    if (sm.sk[lpad(base + m)] <= sm.sk[lpad(base + n1 + dg - 1 - m)]) l = m + 1; else h = m;
+                }
+                uint32_t i1 = base + l, e1 = base + n1, i2 = base + n1 + (dg - l), e2 = base + n1 + n2;
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    const uint32_t x = dx + i;
+                    if (x < nt) {
+                        if (x == nl) {  // this thread's outputs continue into the right child's part
+                            i1 = nl;
+                            e1 = ncl;
+                            i2 = ncl;
+                            e2 = nt;
+                        }
+                        const bool take1 = (i2 >= e2) || (i1 < e1 && sm.sk[lpad(i1)] <= sm.sk[lpad(i2)]);
+                        const uint32_t s = take1 ? i1++ : i2++;
+                        kr[i] = sm.sk[lpad(s)];
+                        if (HP) pr[i] = sm.sp[lpad(s)];
+                    }
+                }
+            }
+            __syncthreads();
+            if (dx < nt) {
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    if (dx + i < nt) {
+                        sm.sk[lpad(dx + i)] = kr[i];
+                        if (HP) sm.sp[lpad(dx + i)] = pr[i];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // The node's merge: sk[0, nl) with sk[nl, nt), left first on equal keys.
+        const uint32_t nrp = nt - nl;
+        if (dx < nt) {
+            uint32_t l = dx > nrp ? dx - nrp : 0, h = min(dx, nl);
+            while (l < h) {
+                const uint32_t m = (l + h) >> 1;
+                if (sm.sk[lpad(m)] <= sm.sk[lpad(nl + dx - 1 - m)]) l = m + 1; else h = m;
+            }
+            uint32_t ia = l, ib = nl + (dx - l);
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                if (dx + i < nt) {
+                    const bool take_a = (ib >= nt) || (ia < nl && sm.sk[lpad(ia)] <= sm.sk[lpad(ib)]);
+                    const uint32_t s = take_a ? ia++ : ib++;
+                    kr[i] = sm.sk[lpad(s)];
+                    if (HP) pr[i] = sm.sp[lpad(s)];
+                }
+            }
+        }
+        __syncthreads();
+        if (dx < nt) {
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                if (dx + i < nt) {
+                    sm.sk[lpad(dx + i)] = kr[i];
+                    if (HP) sm.sp[lpad(dx + i)] = pr[i];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t x = tid + i * NT;
+            if (x < nt) {
+                kr[i] = sm.sk[lpad(x)];
+                if (HP) pr[i] = sm.sp[lpad(x)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t x = tid + i * NT;
+            if (x < nt) {
+                dst[x] = K::unord(kr[i]);
+                if (HP) pdst[x] = pr[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Merges of nodes whose two children are inputs (the head part of pass p's
+// tiles): NT threads x IT outputs per tile (the tile size a.merge_tile),
+// tiles handed out grid-stride.
+template <int KT, bool HP, int NT, int IT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void merge_pass_kernel(MoveArgs a, uint32_t p) {
+    constexpr int TILE = NT * IT;
+    using K = Key<KT>;
+    using U = typename K::ukey;
+    using raw = typename K::raw;
+    __shared__ MergeSharedPad<KT, TILE> sm;
+    const uint32_t sb = a.cnt->sbase[p];
+    // never read past the split records (the tile count is bounded by the
+    // merge cost, so this only guards against inconsistent lists)
+    const uint32_t ntiles = min(a.cnt->ptq[p], a.split_cap > sb ? a.split_cap - sb : 0u);
     const int tid = threadIdx.x;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const SplitRec s0 = a.split[a.cnt->sbase[p] + t];
-        const NodeRec R = a.node_rec[s0.node];
-        const uint32_t tt = t - a.bucket_tile[s0.node];
-        const uint32_t lo = R.lo, mid = R.mid, hi = R.hi;
-        const uint32_t bufs = R.bufs;
-        const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + lo;
-        const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 4) & 3u) + mid;
-        raw* dst = (raw*)pick3u(a.keys, bufs & 3u);
-        const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + lo;
-        const uint32_t* psrcB = pick3u(a.pay, (bufs >> 4) & 3u) + mid;
-        uint32_t* pdst = pick3u(a.pay, bufs & 3u);
-        const uint32_t la = mid - lo, tot = hi - lo;
-        const uint32_t k0 = tt * TILE, k1 = min(tot, k0 + TILE);
-        const uint32_t i0 = s0.corank;
-        const uint32_t i1 = (k1 == tot) ? la : a.split[a.cnt->sbase[p] + t + 1].corank;
-        const uint32_t j0 = k0 - i0, j1 = k1 - i1;
-        const uint32_t na = i1 - i0, nbb = j1 - j0, nt = na + nbb;
+        // the record is the same across the block: keep its fields scalar
+        auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
+        const SplitRec rr = a.split[sb + t];
+        const uint32_t bufs = uni(rr.bufs), out0 = uni(rr.out);
+        const uint32_t sa = uni(rr.s[0]), sc = uni(rr.s[2]), ea = uni(rr.e[0]), ec = uni(rr.e[2]);
+        // consistent records have s <= e, at most TILE outputs and positions
+        // below n; the check only keeps inconsistent lists inside the arrays
+        const uint32_t na = ea > sa ? ea - sa : 0u, nbb = ec > sc ? ec - sc : 0u, nt = na + nbb;
+        if (nt > (uint32_t)TILE || max(ea, ec) > a.n || out0 + nt > a.n) continue;
+        const raw* srcA = (const raw*)pick3u(a.keys, (bufs >> 2) & 3u) + sa;
+        const raw* srcB = (const raw*)pick3u(a.keys, (bufs >> 6) & 3u) + sc;  // the right input C
+        const uint32_t* psrcA = pick3u(a.pay, (bufs >> 2) & 3u) + sa;
+        const uint32_t* psrcB = pick3u(a.pay, (bufs >> 6) & 3u) + sc;
+        raw* dst = (raw*)pick3u(a.keys, bufs & 3u) + out0;
+        uint32_t* pdst = pick3u(a.pay, bufs & 3u) + out0;
         U kr[IT];
         uint32_t pr[IT];
         {
@@ -823,19 +1158,19 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
                 // two masked loads with scalar bases (not a per-lane
                 // pointer select, which costs 64-bit address arithmetic)
                 if (x < na) {
-                    kv[i] = srcA[i0 + x];
-                    if (HP) pr[i] = psrcA[i0 + x];
+                    kv[i] = srcA[x];
+                    if (HP) pr[i] = psrcA[x];
                 } else if (x < nt) {
-                    kv[i] = srcB[j0 + x - na];
-                    if (HP) pr[i] = psrcB[j0 + x - na];
+                    kv[i] = srcB[x - na];
+                    if (HP) pr[i] = psrcB[x - na];
                 }
             }
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 const uint32_t x = tid + i * NT;
                 if (x < nt) {
-                    sm.sk[x] = K::ord(kv[i]);
-                    if (HP) sm.sp[x] = pr[i];
+                    sm.sk[lpad(x)] = K::ord(kv[i]);
+                    if (HP) sm.sp[lpad(x)] = pr[i];
                 }
             }
         }
@@ -845,16 +1180,16 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
             uint32_t l = dx > nbb ? dx - nbb : 0, h = min(dx, na);
             while (l < h) {
                 const uint32_t m = (l + h) >> 1;
-                if (sm.sk[m] <= sm.sk[na + dx - 1 - m]) l = m + 1; else h = m;
+                if (sm.sk[lpad(m)] <= sm.sk[lpad(na + dx - 1 - m)]) l = m + 1; else h = m;
             }
             uint32_t ia = l, ib = na + (dx - l);
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 if (dx + i < nt) {
-                    const bool take_a = (ib >= nt) || (ia < na && sm.sk[ia] <= sm.sk[ib]);
+                    const bool take_a = (ib >= nt) || (ia < na && sm.sk[lpad(ia)] <= sm.sk[lpad(ib)]);
                     const uint32_t s = take_a ? ia++ : ib++;
-                    kr[i] = sm.sk[s];
-                    if (HP) pr[i] = sm.sp[s];
+                    kr[i] = sm.sk[lpad(s)];
+                    if (HP) pr[i] = sm.sp[lpad(s)];
                 }
             }
         }
@@ -863,8 +1198,8 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 if (dx + i < nt) {
-                    sm.sk[dx + i] = kr[i];
-                    if (HP) sm.sp[dx + i] = pr[i];
+                    sm.sk[lpad(dx + i)] = kr[i];
+                    if (HP) sm.sp[lpad(dx + i)] = pr[i];
                 }
             }
         }
@@ -873,16 +1208,16 @@ __global__ __launch_bounds__(NT) void merge_pass_kernel(MoveArgs a, uint32_t p) 
         for (int i = 0; i < IT; ++i) {
             const uint32_t x = tid + i * NT;
             if (x < nt) {
-                kr[i] = sm.sk[x];
-                if (HP) pr[i] = sm.sp[x];
+                kr[i] = sm.sk[lpad(x)];
+                if (HP) pr[i] = sm.sp[lpad(x)];
             }
         }
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const uint32_t x = tid + i * NT;
             if (x < nt) {
-                dst[lo + k0 + x] = K::unord(kr[i]);
-                if (HP) pdst[lo + k0 + x] = pr[i];
+                dst[x] = K::unord(kr[i]);
+                if (HP) pdst[x] = pr[i];
             }
         }
         __syncthreads();
@@ -938,12 +1273,20 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         else if constexpr (sizeof(typename Key<KT>::ukey) == 4)  // 8192: 64 KiB of LDS, 4-byte keys only
             launch(merge_pass_kernel<KT, HP, 1024, 8>, grid, 1024, 0, st, ev0, ev1, a, p);
     }
+    else if (stage == 6) {  // nodes with an absorbed child (two-level passes, 4-byte keys)
+        // 512 threads x 8 outputs per group, whatever the merge tile: four
+        // workgroups per CU keep memory busy through the two LDS merge
+        // phases (1024 x 8 with two per CU: Zipf merges 4.61 -> 4.20 ms)
+        if constexpr (sizeof(typename Key<KT>::ukey) == 4)
+            launch(merge_quad_kernel<KT, HP, 512, 8>, grid, 512, 0, st, ev0, ev1, a, p);
+    }
     else launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
 }
 
 // stage 0: big leaves; 5: single-run fused units (copied); 1: fused
 // subtrees (level by level); 4: fused subtrees with many leaves (radix
-// sort); 2: the merge pass of power p; 3: the split pass of power p.
+// sort); 2: the merge pass of power p; 6: its merges of nodes with an
+// absorbed child; 3: the split pass of power p.
 // ev0 / ev1: optional dispatch events.
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {

@@ -355,14 +355,31 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             if (valid && i >= 1 && P[i] >= 1) {
                 nlf[it] = Lf[i];
                 nrt[it] = Rt[i];
+                // the parent is the nearer of the two bounding boundaries,
+                // the one with the larger power (two ancestors never share
+                // a power; both 0 only at a segment root)
+                const uint32_t pl = P[nlf[it]], pr = P[nrt[it]];
+                const uint32_t par = pl > pr ? nlf[it] : (pr > pl ? nrt[it] : kNone);
+                if (par == nrt[it]) L.child_l[par] = i;
+                else if (par != kNone) L.child_r[par] = i;
                 const uint32_t sz = nsize[i];
                 if (sz > (uint32_t)kFuse) {
-                    f |= 1;  // big node
-                    pr_merge += sz;
-                } else {
-                    const uint32_t pl = P[nlf[it]], pr = P[nrt[it]];
-                    const uint32_t par = pl > pr ? nlf[it] : (pr > pl ? nrt[it] : kNone);
-                    if ((par == kNone) || size_of(par) > (uint32_t)kFuse) f |= 2;  // unit node
+                    // a merge of its own pass, unless two-level passes absorb
+                    // it into its parent (big nodes at odd depth)
+                    if (L.levels != 2 || (node_depth[i] & 1u) == 0) {
+                        f |= 1;
+                        pr_merge += sz;
+                        // does it absorb a child: one of more than kFuse
+                        // elements that is not a single leaf
+                        if (L.levels == 2) {
+                            const uint32_t s0 = starts[nlf[it]], sm = starts[i], s1 = starts[nrt[it]];
+                            if ((nlf[it] + 1 < i && sm - s0 > (uint32_t)kFuse) ||
+                                (i + 1 < nrt[it] && s1 - sm > (uint32_t)kFuse))
+                                f |= 16;
+                        }
+                    }
+                } else if ((par == kNone) || size_of(par) > (uint32_t)kFuse) {
+                    f |= 2;  // unit node
                 }
             }
             // ---- leaf i
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                 if (len > (uint32_t)kFuse) {
                     f |= 8;  // big leaf
                     const bool desc = K::ord(keys[s + 1]) < K::ord(keys[s]);
-                    const bool moved = big_leaf_buf(leaf_depth[i], L.nbuf) != 0;
+                    const bool moved = big_leaf_buf(pass_level(leaf_depth[i], L.levels), L.nbuf) != 0;
                     mode[it] = desc ? (moved ? kLeafRevCopy : kLeafRevInPlace) : (moved ? kLeafCopy : kLeafNoop);
                 } else if ((par == kNone) || size_of(par) > (uint32_t)kFuse) {
                     f |= 4;  // unit leaf
@@ -408,18 +425,18 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
         for (int it = 0; it < kIt; ++it) {
             const uint32_t i = i0 + it * kThreads + threadIdx.x;
             const uint8_t f = fl[it];
-            if (f & 1) L.biglist[pos[0]++] = i;
+            if (f & 1) L.biglist[pos[0]++] = i | ((f & 16) ? 0x80000000u : 0u);
             if (f & 2) {
                 const uint32_t slot = pos[1]++;
                 pr_fused += starts[nrt[it]] - starts[nlf[it]];
                 L.unit_rec[slot] = UnitRec{nlf[it], nrt[it], starts[nlf[it]], starts[nrt[it]]};
-                L.unit_par[slot] = node_buf(node_depth[i], L.nbuf);
+                L.unit_par[slot] = node_buf(pass_level(node_depth[i], L.levels), L.nbuf);
             }
             if (f & 4) {
                 const uint32_t slot = pos[2]++;
                 pr_fused += starts[i + 1] - starts[i];
                 L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
-                L.unit_par[slot] = node_buf(leaf_depth[i], L.nbuf);
+                L.unit_par[slot] = node_buf(pass_level(leaf_depth[i], L.levels), L.nbuf);
             }
             if (f & 8) {
                 const uint32_t slot = pos[3]++;
@@ -467,23 +484,34 @@ __device__ __forceinline__ uint32_t wave_count_by_key(bool active, uint32_t key,
     return slot;
 }
 
-// Big nodes per power: counted per block in LDS, then one atomic per
-// power per block (a few dozen global counters take every update).
+// The bucket key of a big-node list entry: 2 p + 1 for a node of power p
+// that absorbs a child, 2 p otherwise.  Within its power's bucket a node that
+// absorbs a child comes after every node that does not.
+__device__ __forceinline__ uint32_t bucket_key(const uint8_t* __restrict__ P, uint32_t e) {
+    return 2u * P[e & 0x7FFFFFFFu] + (e >> 31);
+}
+constexpr int kKeys = 2 * (kMaxPass + 1);
+
+// Big nodes per power (and how many absorb a child): counted per block in
+// LDS, then one atomic per key per block (a few dozen global counters take
+// every update).
 __global__ __launch_bounds__(kThreads) void bucket_count_kernel(const uint8_t* __restrict__ P,
                                                                  Counters* __restrict__ cnt, TreeLists L) {
-    __shared__ uint32_t h[kMaxPass + 1];
+    __shared__ uint32_t h[kKeys];
     const uint32_t nbig = cnt->nbig;
-    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kKeys; i += kThreads) h[i] = 0;
     __syncthreads();
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nbig;
-        const uint32_t p = valid ? P[L.biglist[k]] : 0;
-        wave_count_by_key(valid, p, h);
+        wave_count_by_key(valid, valid ? bucket_key(P, L.biglist[k]) : 0u, h);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads)
-        if (h[i]) atomicAdd(&cnt->pcount[i], h[i]);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kKeys; i += kThreads) {
+        if (!h[i]) continue;
+        atomicAdd(&cnt->pcount[i >> 1], h[i]);
+        if (i & 1u) atomicAdd(&cnt->pcount_q[i >> 1], h[i]);
+    }
 }
 
 __global__ void bucket_base_kernel(Counters* cnt) {
@@ -492,35 +520,41 @@ __global__ void bucket_base_kernel(Counters* cnt) {
         for (int p = 0; p <= kMaxPass; ++p) {
             cnt->pbase[p] = acc;
             cnt->pfill[p] = 0;
+            cnt->pqfill[p] = 0;
             acc += cnt->pcount[p];
         }
     }
 }
 
-// Each block counts its nodes per power in LDS, reserves that many slots
-// of every bucket with one atomic per power, then hands them out in LDS.
+// Each block counts its nodes per key in LDS, reserves that many slots of
+// every bucket with one atomic per key (nodes that absorb a child from the
+// bucket's tail part), then hands them out in LDS.
 __global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(const uint8_t* __restrict__ P,
                                                                    Counters* __restrict__ cnt, TreeLists L) {
-    __shared__ uint32_t h[kMaxPass + 1];
+    __shared__ uint32_t h[kKeys];
     const uint32_t nbig = cnt->nbig;
-    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kKeys; i += kThreads) h[i] = 0;
     __syncthreads();
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nbig;
-        wave_count_by_key(valid, valid ? P[L.biglist[k]] : 0u, h);
+        wave_count_by_key(valid, valid ? bucket_key(P, L.biglist[k]) : 0u, h);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxPass; i += kThreads)
-        if (h[i]) h[i] = cnt->pbase[i] + atomicAdd(&cnt->pfill[i], h[i]);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kKeys; i += kThreads) {
+        if (!h[i]) continue;
+        const uint32_t p = i >> 1;
+        h[i] = (i & 1u) ? cnt->pbase[p] + (cnt->pcount[p] - cnt->pcount_q[p]) + atomicAdd(&cnt->pqfill[p], h[i])
+                        : cnt->pbase[p] + atomicAdd(&cnt->pfill[p], h[i]);
+    }
     __syncthreads();
-    // h[p] is now the block's next free slot of bucket p
+    // h[key] is now the block's next free slot of that part of its bucket
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nbig; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nbig;
-        const uint32_t j = valid ? L.biglist[k] : 0;
-        const uint32_t slot = wave_count_by_key(valid, valid ? P[j] : 0u, h);
-        if (valid) L.bucket[slot] = j;
+        const uint32_t e = valid ? L.biglist[k] : 0;
+        const uint32_t slot = wave_count_by_key(valid, valid ? bucket_key(P, e) : 0u, h);
+        if (valid) L.bucket[slot] = e & 0x7FFFFFFFu;
     }
 }
 
@@ -556,16 +590,49 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
                 const uint32_t j = L.bucket[off + k];
                 const uint32_t lf = Lf[j], rt = Rt[j];
                 const uint32_t lo = starts[lf], mid = starts[j], hi = starts[rt];
-                // A child that is one leaf longer than a fused subtree is in
-                // the long-leaf array; any other child is a node or a fused
-                // subtree, in its depth's array.
                 const uint32_t d = node_depth[j];
-                const uint32_t ba = (lf + 1 == j && mid - lo > (uint32_t)kFuse) ? big_leaf_buf(d + 1, L.nbuf)
-                                                                                 : node_buf(d + 1, L.nbuf);
-                const uint32_t bb = (j + 1 == rt && hi - mid > (uint32_t)kFuse) ? big_leaf_buf(d + 1, L.nbuf)
-                                                                                 : node_buf(d + 1, L.nbuf);
-                L.node_rec[off + k] = NodeRec{lo, mid, hi, node_buf(d, L.nbuf) | (ba << 2) | (bb << 4)};
-                tiles[it] = (hi - lo + merge_tile - 1) / merge_tile;
+                // An input of the merge that is one leaf longer than a fused
+                // subtree is in the long-leaf array; any other input is a
+                // node or a fused subtree, in its pass level's array.
+                auto in_buf = [&](bool one_leaf, uint32_t size, uint32_t depth) -> uint32_t {
+                    const uint32_t lv = pass_level(depth, L.levels);
+                    return (one_leaf && size > (uint32_t)kFuse) ? big_leaf_buf(lv, L.nbuf) : node_buf(lv, L.nbuf);
+                };
+                // A child of more than kFuse elements that is not one leaf is
+                // a big node; at odd depth, with two-level passes, it is
+                // merged here: its children are the inputs.
+                uint32_t m1 = mid, m2 = hi, ba, bb = 0, bc, bd = 0;
+                // (a child index outside the node's leaves would mean
+                // inconsistent lists: the child is then taken as an input,
+                // which keeps every access inside the node)
+                const uint32_t kl = (L.levels == 2 && lf + 1 < j) ? L.child_l[j] : 0u;
+                const uint32_t kr = (L.levels == 2 && j + 1 < rt) ? L.child_r[j] : 0u;
+                if (L.levels == 2 && lf + 1 < j && mid - lo > (uint32_t)kFuse && kl > lf && kl < j) {
+                    m1 = starts[kl];
+                    ba = in_buf(lf + 1 == kl, m1 - lo, d + 2);
+                    bb = in_buf(kl + 1 == j, mid - m1, d + 2);
+                } else {
+                    ba = in_buf(lf + 1 == j, mid - lo, d + 1);
+                }
+                if (L.levels == 2 && j + 1 < rt && hi - mid > (uint32_t)kFuse && kr > j && kr < rt) {
+                    m2 = starts[kr];
+                    bc = in_buf(j + 1 == kr, m2 - mid, d + 2);
+                    bd = in_buf(kr + 1 == rt, hi - m2, d + 2);
+                } else {
+                    bc = in_buf(j + 1 == rt, hi - mid, d + 1);
+                }
+                const NodeRec R{lo, m1, mid, m2, hi,
+                                node_buf(pass_level(d, L.levels), L.nbuf) | (ba << 2) | (bb << 4) | (bc << 6) |
+                                    (bd << 8)};
+                L.node_rec[off + k] = R;
+                if (node_is_quad(R)) {
+                    // boundaries every kQuadSpacing along each child's merge,
+                    // plus the start
+                    const uint32_t g = kQuadSpacing;
+                    tiles[it] = (mid - lo - 1) / g + (hi - mid - 1) / g + 1;
+                } else {
+                    tiles[it] = (hi - lo + merge_tile - 1) / merge_tile;
+                }
             }
             sum += tiles[it];
         }
@@ -577,12 +644,17 @@ __global__ __launch_bounds__(kThreads) void tile_scan_kernel(const uint32_t* __r
             if (k < n) {
                 if (p == 0) L.leaf_tile[k] = run;
                 else L.bucket_tile[off + k] = run;
+                // the first node that absorbs a child starts the pass's second part
+                if (p > 0 && k == n - cnt->pcount_q[p]) cnt->ptq[p] = run;
             }
             run += tiles[it];
         }
         carry += total;
     }
-    if (threadIdx.x == 0) cnt->ptiles[p] = carry;
+    if (threadIdx.x == 0) {
+        cnt->ptiles[p] = carry;
+        if (p > 0 && cnt->pcount_q[p] == 0) cnt->ptq[p] = carry;
+    }
 }
 
 // First split record of every pass.

@@ -87,8 +87,9 @@ def test_workspace_bytes(lib):
     nopay = lib.ps_workspace_bytes(1 << 28, 1, 0, 0, None)
     assert 0 < small < big < wide
     assert nopay < big
-    # scratch for two copies of keys+payload plus metadata well below the data size
-    assert 2 * (1 << 28) * 8 <= big < 2 * (1 << 28) * 8 * 1.25
+    # scratch for two copies of keys+payload plus metadata well below the data
+    # size (the merge-tile records are sized by the bound M <= n (lg n + 2))
+    assert 2 * (1 << 28) * 8 <= big < 2 * (1 << 28) * 8 * 1.4
     # PS_FLAG_COMPACT_SCRATCH: one copy
     compact = lib.ps_workspace_bytes(1 << 28, 1, 0, 1, _opts(binding, flags=2))
     assert big - compact == (1 << 28) * 8
@@ -115,6 +116,11 @@ def test_tuning_roundtrip_on_host():
     assert binding.get_tuning()["merge_tile"] == 8192
     with pytest.raises(binding.PowersortError):
         binding.set_tuning({"grid_split": 1 << 20})
+    with pytest.raises(binding.PowersortError):
+        binding.set_tuning({"merge_levels": 3})
+    assert binding.get_tuning()["merge_levels"] == 1
+    binding.set_tuning({"merge_levels": 2})
+    assert binding.get_tuning()["merge_levels"] == 2
     binding.set_tuning(None)
     assert binding.get_tuning() == d
 

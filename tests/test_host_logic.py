@@ -85,6 +85,7 @@ def test_autotuner_search_space():
         for c in cands:
             assert set(c) <= set(TUNING_FIELDS)
             assert c["merge_tile"] in (2048, 4096, 8192)
+            assert c["merge_levels"] in (1, 2)
             assert all(1 <= c[k] <= 65536 for k in c if k.startswith("grid_"))
     import torch
     assert autotune.signature(3 << 20, 4096, torch.int32, None) == autotune.signature(2 << 20, 5000, torch.int32, 24)
