@@ -33,6 +33,13 @@ Parity status per function (pins live in the tests' oracle-pin suite):
                        inputs, n - 1 for run detection plus at most size - 1
                        per merge, and the comparison bounds of Thm.
                        "powersort" and "peeksort"
+  powersort(galloping=True)
+                       pinned: the same output, merges and merge cost as the
+                       plain merges and the library stable sort; at least the
+                       information bound lg C(a+b, a) per merge; exactly the
+                       plain count when the output alternates between runs;
+                       logarithmic cost per block when runs supply long
+                       blocks
 """
 from __future__ import annotations
 
@@ -102,6 +109,8 @@ def _load():
         lib.oracle_powersort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                          ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          u64p, u64p]
+        lib.oracle_powersort_galloping.restype = ctypes.c_int
+        lib.oracle_powersort_galloping.argtypes = lib.oracle_powersort.argtypes
         lib.oracle_segmented_powersort.restype = ctypes.c_int
         lib.oracle_segmented_powersort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
@@ -161,8 +170,10 @@ class Result:
 
 
 def powersort(keys: np.ndarray, payload: np.ndarray | None = None, min_run: int = DEFAULT_MIN_RUN,
-              details: bool = True) -> Result:
-    """Run the oracle on copies of keys/payload; inputs are left untouched."""
+              details: bool = True, galloping: bool = False) -> Result:
+    """Run the oracle on copies of keys/payload; inputs are left untouched.
+    galloping: merge with Timsort-style galloping (same result and merge
+    cost, fewer comparisons when runs supply long blocks)."""
     lib = _load()
     kt = key_type_of(keys)
     k = np.ascontiguousarray(keys).copy()
@@ -176,8 +187,9 @@ def powersort(keys: np.ndarray, payload: np.ndarray | None = None, min_run: int 
         merges = np.zeros((max(n, 1), 3), np.uint64)
     else:
         starts = powers = merges = None
-    rc = lib.oracle_powersort(_ptr(k), _ptr(p), n, KEY_TYPES[kt], min_run, _ptr(starts), _ptr(powers),
-                              _ptr(merges), ctypes.byref(r), ctypes.byref(M))
+    fn = lib.oracle_powersort_galloping if galloping else lib.oracle_powersort
+    rc = fn(_ptr(k), _ptr(p), n, KEY_TYPES[kt], min_run, _ptr(starts), _ptr(powers),
+            _ptr(merges), ctypes.byref(r), ctypes.byref(M))
     if rc != 0:
         raise RuntimeError("oracle_powersort failed")
     rr = r.value

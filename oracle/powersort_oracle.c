@@ -34,7 +34,11 @@
  * the run convention, the powers against the paper's Fig. 1 values and an
  * exact-rational evaluation, the merge list against the Cartesian tree of the
  * powers (Cor. "Cartesian tree"), and the merge cost against Fig. 1, the
- * entropy bounds of Thm. "powersort" and an interval-DP optimum.
+ * entropy bounds of Thm. "powersort" and an interval-DP optimum.  The
+ * galloping merge is pinned by equality with the plain merge's result and
+ * merge cost, the information bound on comparisons per merge, equality with
+ * the plain count on alternating merges, and a logarithmic cost per block on
+ * block merges.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -166,6 +170,78 @@ static void merge_runs(arr_t *A, uint64_t lo, uint64_t mid, uint64_t hi,
     if (A->pay) memcpy(A->pay + lo, tp, (hi - lo) * sizeof(uint32_t));
 }
 
+/* Galloping merge (the comparison-saving merge of Timsort that Sec. 4.1
+ * describes and Sec. 5 names for future comparison-efficient merging): a
+ * plain merge that counts how many times in a row each run has supplied the
+ * output; once one run has won kGallop times in a row it switches to
+ * exponential searches -- the number of left elements not above the right
+ * head, then the number of right elements below the left head -- and copies
+ * those blocks whole, until both searches return fewer than kGallop
+ * elements.  Equal keys still go left first, so the result is exactly
+ * merge_runs's; only the comparisons differ.  The paper fixes no threshold;
+ * kGallop = 7 is Timsort's.  (Peters' adaptive threshold is not used.) */
+enum { kGallop = 7 };
+
+/* Exponential then binary search: the number of elements of A[s..e) that
+ * precede key v in a stable merge where A is the LEFT run (those not above
+ * v: !(v < x)) if left_run, else where A is the RIGHT run (those strictly
+ * below v). */
+static uint64_t gallop_count(const arr_t *A, uint64_t s, uint64_t e, const unsigned char *v, int left_run) {
+    uint64_t lo = 0, hi = 1, len = e - s;  /* the count lies in (lo - 1 ... ] as probed */
+    /* goes(k): element s + k precedes v */
+    #define GOES(k) (left_run ? !key_less(A, v, A->key + (s + (k)) * A->ks) \
+                              : key_less(A, A->key + (s + (k)) * A->ks, v))
+    if (len == 0 || !GOES(0)) return 0;
+    /* invariant: elements [0, lo] go; probe lo + hi */
+    while (lo + hi < len && GOES(lo + hi)) { lo += hi; hi *= 2; }
+    /* elements [0, lo] go; element min(lo + hi, len) does not (or is past the end) */
+    uint64_t a = lo + 1, b = (lo + hi < len) ? lo + hi : len;  /* count in [a, b] */
+    while (a < b) {
+        uint64_t m = a + (b - a) / 2;  /* does element m go? */
+        if (GOES(m)) a = m + 1; else b = m;
+    }
+    #undef GOES
+    return a;
+}
+
+/* Append element src to the merge buffer at o. */
+static void take_one(const arr_t *A, uint64_t src, unsigned char *tk, uint32_t *tp, uint64_t *o) {
+    memcpy(tk + *o * A->ks, A->key + src * A->ks, A->ks);
+    if (A->pay) tp[*o] = A->pay[src];
+    (*o)++;
+}
+
+static void merge_runs_galloping(arr_t *A, uint64_t lo, uint64_t mid, uint64_t hi,
+                                 unsigned char *tk, uint32_t *tp) {
+    uint64_t i = lo, j = mid, o = 0;
+    size_t ks = A->ks;
+    unsigned wins_left = 0, wins_right = 0;
+#define TAKE(src) take_one(A, (src), tk, tp, &o)
+    while (i < mid && j < hi) {
+        if (wins_left < kGallop && wins_right < kGallop) {
+            if (less_at(A, j, i)) { TAKE(j); j++; wins_right++; wins_left = 0; }
+            else { TAKE(i); i++; wins_left++; wins_right = 0; }
+            continue;
+        }
+        /* galloping mode */
+        for (;;) {
+            uint64_t c = gallop_count(A, i, mid, A->key + j * ks, 1);
+            for (uint64_t t = 0; t < c; t++) { TAKE(i); i++; }
+            if (i == mid) break;
+            uint64_t d = gallop_count(A, j, hi, A->key + i * ks, 0);
+            for (uint64_t t = 0; t < d; t++) { TAKE(j); j++; }
+            if (j == hi) break;
+            if (c < kGallop && d < kGallop) break;
+        }
+        wins_left = wins_right = 0;
+    }
+    while (i < mid) { TAKE(i); i++; }
+    while (j < hi) { TAKE(j); j++; }
+#undef TAKE
+    memcpy(A->key + lo * ks, tk, (hi - lo) * ks);
+    if (A->pay) memcpy(A->pay + lo, tp, (hi - lo) * sizeof(uint32_t));
+}
+
 static size_t key_size(int type) {
     return (type == ORK_I64 || type == ORK_U64) ? 8 : 4;
 }
@@ -184,12 +260,16 @@ typedef struct {
     unsigned char *tk;
     uint32_t *tp;
     ora_merge *merges;  /* optional record of merges in execution order */
+    int galloping;      /* merge with merge_runs_galloping */
     uint8_t *powers;    /* optional record of boundary powers, left to right */
     uint64_t nm, np, M;
 } sched_t;
 
 static void do_merge(sched_t *S, uint64_t lo, uint64_t mid, uint64_t hi) {
-    if (S->A) merge_runs(S->A, lo, mid, hi, S->tk, S->tp);
+    if (S->A) {
+        if (S->galloping) merge_runs_galloping(S->A, lo, mid, hi, S->tk, S->tp);
+        else merge_runs(S->A, lo, mid, hi, S->tk, S->tp);
+    }
     if (S->merges) { S->merges[S->nm].lo = lo; S->merges[S->nm].mid = mid; S->merges[S->nm].hi = hi; }
     S->nm++;
     S->M += hi - lo; /* merge cost of one merge = size of its result (Sec. 2.2) */
@@ -248,9 +328,9 @@ static uint64_t next_leaf(arr_t *A, uint64_t s, uint64_t n, uint32_t w) {
  * r_out receives r, merge_cost_out receives M.  Returns 0, or -1 on bad
  * arguments or allocation failure.
  */
-int oracle_powersort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
-                     uint64_t *starts, uint8_t *powers, ora_merge *merges,
-                     uint64_t *r_out, uint64_t *merge_cost_out) {
+static int powersort_impl(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
+                          uint64_t *starts, uint8_t *powers, ora_merge *merges,
+                          uint64_t *r_out, uint64_t *merge_cost_out, int galloping) {
     if (type < ORK_I32 || type > ORK_F32 || w < 1) return -1;
     arr_t A = { (unsigned char *)keys, payload, key_size(type), type };
     g_comparisons = 0;
@@ -267,6 +347,7 @@ int oracle_powersort(void *keys, uint32_t *payload, uint64_t n, int type, uint32
     S.A = &A;
     S.merges = merges;
     S.powers = powers;
+    S.galloping = galloping;
     S.tk = (unsigned char *)malloc(n * A.ks);
     S.tp = (uint32_t *)malloc(n * sizeof(uint32_t));
     if (!S.tk || !S.tp) { free(S.tk); free(S.tp); return -1; }
@@ -289,6 +370,20 @@ int oracle_powersort(void *keys, uint32_t *payload, uint64_t n, int type, uint32
     free(S.tk);
     free(S.tp);
     return 0;
+}
+
+int oracle_powersort(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
+                     uint64_t *starts, uint8_t *powers, ora_merge *merges,
+                     uint64_t *r_out, uint64_t *merge_cost_out) {
+    return powersort_impl(keys, payload, n, type, w, starts, powers, merges, r_out, merge_cost_out, 0);
+}
+
+/* oracle_powersort with galloping merges: the same runs, tree, merges, merge
+ * cost and result; only the key comparisons differ. */
+int oracle_powersort_galloping(void *keys, uint32_t *payload, uint64_t n, int type, uint32_t w,
+                               uint64_t *starts, uint8_t *powers, ora_merge *merges,
+                               uint64_t *r_out, uint64_t *merge_cost_out) {
+    return powersort_impl(keys, payload, n, type, w, starts, powers, merges, r_out, merge_cost_out, 1);
 }
 
 /* The merge order of Alg. PowerSort for given run lengths L[0..r) (no data):

@@ -71,15 +71,31 @@ MERGESORT_MUTANTS = {
 }
 
 
+# Mistakes in the galloping merge, checked against its pins.
+GALLOP_MUTANTS = {
+    # the right run's gallop also takes keys equal to the left head (ties go right)
+    "gallop_right_nonstrict": (": key_less(A, A->key + (s + (k)) * A->ks, v))",
+                               ": !key_less(A, v, A->key + (s + (k)) * A->ks))"),
+    # the binary search after the exponential one skips the first candidate
+    "gallop_binary_start": ("uint64_t a = lo + 1, b = (lo + hi < len) ? lo + hi : len;",
+                            "uint64_t a = lo + 2, b = (lo + hi < len) ? lo + hi : len;"),
+    # galloping mode is never entered
+    "gallop_never": ("if (wins_left < kGallop && wins_right < kGallop) {", "if (1) {"),
+}
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PEEK_MUTANTS) + sorted(MERGESORT_MUTANTS))
+@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PEEK_MUTANTS) + sorted(MERGESORT_MUTANTS)
+                         + sorted(GALLOP_MUTANTS))
 def test_pins_reject_planted_mistake(tmp_path, name):
     if name in MUTANTS:
         (a, b), suite = MUTANTS[name], "tests/test_oracle_pins.py"
     elif name in PEEK_MUTANTS:
         (a, b), suite = PEEK_MUTANTS[name], "tests/test_oracle_peeksort.py"
-    else:
+    elif name in MERGESORT_MUTANTS:
         (a, b), suite = MERGESORT_MUTANTS[name], "tests/test_oracle_mergesorts.py"
+    else:
+        (a, b), suite = GALLOP_MUTANTS[name], "tests/test_oracle_galloping.py"
     src = open(os.path.join(ROOT, "oracle", "powersort_oracle.c")).read()
     assert a in src, "mutation site not found"
     ign = shutil.ignore_patterns("*.so", "*.tmp", "__pycache__")

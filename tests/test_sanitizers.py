@@ -27,7 +27,7 @@ def test_oracle_pins_under_asan_and_ubsan():
     import oracle
     lib = oracle.build_sanitized()
     suites = ["tests/test_oracle_pins.py", "tests/test_oracle_peeksort.py", "tests/test_oracle_mergesorts.py",
-              "tests/test_oracle_comparisons.py"]
+              "tests/test_oracle_comparisons.py", "tests/test_oracle_galloping.py"]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-s", "-p", "no:cacheprovider", "-k",
                         "not printed_in_sec4", *suites], cwd=ROOT, env=sanitized_env(lib),
                        capture_output=True, text=True, timeout=900)
