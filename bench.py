@@ -86,9 +86,10 @@ def merge_kernel_digest() -> str:
     """Digest of the merge-pass kernels' source text (their LDS layout and
     bodies: the two-input and the four-input merge)."""
     src = open(os.path.join(ROOT, "paper_1805_04154_amd", "csrc", "merge.hip")).read()
-    parts = []
-    for start in ("__device__ __forceinline__ uint32_t lpad(", "void merge_quad_kernel(MoveArgs a, uint32_t p) {",
-                  "void merge_pass_kernel(MoveArgs a, uint32_t p) {"):
+    a = src.index("__device__ __forceinline__ uint32_t lpad(")
+    parts = [src[a:src.index("\n", a)]]  # the one-line padding function
+    for start in ("void merge_quad_kernel(MoveArgs a, uint32_t p) {", "void merge_pass_kernel(MoveArgs a, uint32_t p) {",
+                  "void put_samples_lds("):
         a = src.index(start)
         parts.append(src[a:src.index("\n}\n", a)])
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
@@ -953,8 +954,9 @@ def run_mergecost(args) -> int:
 
 def mergecost_cpu_baseline(fams, host_keys, rows, w) -> dict:
     """The oracle on every family, one pinned core: powersort's merge cost
-    (must equal the GPU's) and time, and the merge costs of the paper's
-    top-down and bottom-up mergesorts (Sec. 4.1)."""
+    (must equal the GPU's) and time, the merge costs of the paper's
+    top-down and bottom-up mergesorts (Sec. 4.1), and powersort's key
+    comparisons with plain and with galloping merges (Sec. 4.1, Sec. 5)."""
     import oracle
 
     def work():
@@ -969,16 +971,22 @@ def mergecost_cpu_baseline(fams, host_keys, rows, w) -> dict:
                 return {"error": f"{name}: the oracle's merge cost differs from the GPU's"}
             td = oracle.topdown_mergesort(k, None, min_run=w).merge_cost
             bu = oracle.bottomup_mergesort(k, None, min_run=w).merge_cost
+            gal = oracle.powersort(k, None, min_run=w, details=False, galloping=True)
+            if gal.merge_cost != ps.merge_cost:
+                return {"error": f"{name}: galloping merges changed the oracle's merge cost"}
             out.append({"family": name, "M_over_n_powersort": round(ps.merge_cost / n, 4),
                         "M_over_n_topdown_mergesort": round(td / n, 4),
-                        "M_over_n_bottomup_mergesort": round(bu / n, 4)})
+                        "M_over_n_bottomup_mergesort": round(bu / n, 4),
+                        "comparisons_per_key_plain_merge": round(ps.comparisons / n, 4),
+                        "comparisons_per_key_galloping_merge": round(gal.comparisons / n, 4)})
         return {"families": out, "keys": nk, "secs": secs}
 
     r, core = run_pinned(work)
     if "error" in r:
         return r
     return {"value": round(r["keys"] / r["secs"], 1), "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"every family once: oracle powersort (timed), top-down and bottom-up mergesort; one "
+            "sample": f"every family once: oracle powersort (timed), top-down and bottom-up mergesort, powersort "
+                      f"with galloping merges; one "
                       f"thread pinned to host core {core} ({host_cpu()})",
             "families": r["families"]}
 

@@ -196,9 +196,9 @@ ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uin
  * still owns keys, payload and d_merge_cost.  opt->workspace must be NULL
  * (PS_ERR_INVALID_ARG otherwise).  A sort whose ps_workspace_bytes(n, 1,
  * key_type, payload != NULL, opt) exceeds 128 MiB returns PS_ERR_TOO_LARGE
- * with nothing enqueued; at the default minimum run that is above 6 750 752
- * 4-byte keys with a payload (11 292 832 without) or 4 813 775 8-byte keys
- * with a payload (6 750 768 without).  All calls on one device share that device's
+ * with nothing enqueued; at the default minimum run that is above 6 418 560
+ * 4-byte keys with a payload (10 396 224 without) or 4 656 864 8-byte keys
+ * with a payload (6 428 111 without).  All calls on one device share that device's
  * array, and each call rewrites what it needs: calls that overlap on one
  * device (on different streams or from different threads) race and give
  * undefined results, so the caller serialises them, e.g. on one stream.
@@ -215,7 +215,7 @@ ps_status ps_sort_no_alloc(void *keys, uint32_t *payload, uint64_t n, ps_key_typ
  * in the merge tree is not written out but merged in the same pass as its
  * parent, which then merges up to four inputs.
  * Defaults: merge_tile 8192, merge_levels 1, grid_merge 2048, grid_split
- * 512, grid_fused 2048, grid_big_leaf 2048.
+ * 2048, grid_fused 2048, grid_big_leaf 2048.
  * Zero fields keep their current value.  Written by the project's
  * autotuner for a workload; read back with ps_get_tuning. */
 typedef struct {

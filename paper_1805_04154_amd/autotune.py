@@ -33,7 +33,7 @@ def candidates(small: bool = False) -> list[dict]:
     tiles = (8192, 4096, 2048)
     merge_grids = (1024, 2048, 4096) if not small else (2048,)
     fused_grids = (1024, 2048) if not small else (2048,)
-    split_grids = (256, 512, 1024) if not small else (512,)
+    split_grids = (1024, 2048, 4096) if not small else (2048,)
     out = []
     for lv, t, gm, gf, gs in itertools.product(levels, tiles, merge_grids, fused_grids, split_grids):
         out.append({"merge_levels": lv, "merge_tile": t, "grid_merge": gm, "grid_fused": gf, "grid_split": gs,

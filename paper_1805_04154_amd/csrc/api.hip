@@ -165,6 +165,7 @@ struct Layout {
     size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt, nsize;
     size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split, span;
     size_t child_l, child_r;
+    size_t samp = 0;  // 4-byte keys that move: one order key per kSampleSpacing positions
     uint32_t rmax;
     uint64_t split_cap = 0;
     size_t peek_f[2] = {0, 0};  // peeksort frontiers (ranges of one depth)
@@ -246,6 +247,7 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
         L.split_cap = merged / kQuadSpacing + merged / kFuse + 64;
         L.split = take(at, L.split_cap * sizeof(SplitRec));
         L.span = take(at, L.split_cap * sizeof(TileSpan));
+        if (kb == 4) L.samp = take(at, (N + kSampleSpacing - 1) / kSampleSpacing * 4);
     } else {
         L.unit_rec = L.unit_par = L.bigleaf = L.bigleaf_mode = L.biglist = L.bucket = L.node_rec = L.bucket_tile = L.leaf_tile = 0;
         L.child_l = L.child_r = 0;
@@ -549,6 +551,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     pa.starts = (uint32_t*)at(L.starts);
     pa.r_dev = (uint32_t*)cnt;  // Counters.r is its first word
     pa.rmax = L.rmax;
+    pa.samp = (moves && kb == 4) ? (uint32_t*)at(L.samp) : nullptr;
     {
         ProfScope ps_(PS_PROF_PARTITION, 2 + 2 * L.levels, c.N, st, c.prof);
         e = launch_partition(c.kt, pa, st);
@@ -643,9 +646,9 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.split = (SplitRec*)at(L.split);
         ma.span = (TileSpan*)at(L.span);
         ma.split_cap = (uint32_t)std::min<uint64_t>(L.split_cap, 0xFFFFFFFFull);
-        ma.fuse_max_leaves = fuse_max_leaves(c.w);
         ma.merge_tile = merge_tile;
         ma.n = N;
+        ma.samp = pa.samp;
         // Powers: by the definition of a node power, P_j <= ceil(lg(2n / (L_{j-1}
         // + L_j))), and two adjacent leaves of a segment hold at least w + 1
         // elements (only a segment's last leaf may be shorter than w), so no
@@ -679,6 +682,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
             // tile co-ranks: a split pass for 4-byte keys; 8-byte keys find
             // them inside the merge pass
             if (kb == 4) e = stage(PS_PROF_SPLIT, 3, p, tune.grid_split);
+            if (e == hipSuccess && ta.lists.levels == 2) e = stage(PS_PROF_SPLIT, 7, p, tune.grid_split);
             if (e == hipSuccess) e = stage(PS_PROF_MERGE, 2, p, tune.grid_merge);
             if (e == hipSuccess && ta.lists.levels == 2) e = stage(PS_PROF_MERGE, 6, p, tune.grid_merge);
         }

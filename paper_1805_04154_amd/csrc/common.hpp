@@ -71,14 +71,12 @@ constexpr int kFuseItems = 8;
 constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
 // A fused subtree with at least this many leaves is sorted by the block
 // radix sort instead of level-by-level merges (any key width: 8-byte keys
-// need 108 KiB of LDS, one block per CU, and still win on permutations).
+// need 108 KiB of LDS, one block per CU, and still win on permutations);
+// smaller ones hold at most kFuseRadixMinLeaves - 2 merges.
 constexpr uint32_t kFuseRadixMinLeaves = 8;
 __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nleaves) {
     return (key_bytes == 4 || key_bytes == 8) && nleaves >= kFuseRadixMinLeaves;
 }
-// Leaves in a subtree of kFuse elements: at most kFuse / w + 1 (all but the
-// last leaf of a segment hold >= w elements; natural runs hold >= 2).
-__host__ __device__ constexpr uint32_t fuse_max_leaves(uint32_t w) { return kFuse / (w < 2 ? 2 : w) + 1; }
 
 // Global merge passes: merge-path tiles of 8192 outputs (1024 threads x 8)
 // by default for 4-byte keys, which halves the split searches; 8-byte keys
@@ -91,6 +89,13 @@ constexpr uint32_t kMergeTileMin = 2048;
 // the merge pass packs consecutive tiles into groups of up to kQuadTile.
 constexpr uint32_t kQuadSpacing = 1024;
 constexpr uint32_t kQuadTile = 4096;
+// Splitter search (4-byte keys): every position divisible by kSampleSpacing
+// keeps a copy of its current order key in a small sample array, so that a
+// merge-path co-rank is first found among the samples (a few cached lines)
+// and then within fewer than 2 kSampleSpacing positions of the runs.  The
+// search is k-ary: kSplitGroup lanes probe evenly spaced points per round.
+constexpr uint32_t kSampleSpacing = 128;
+constexpr int kSplitGroup = 16;
 
 // Copy/reverse of leaves longer than kFuse.
 constexpr int kLeafTile = 16384;
@@ -126,8 +131,8 @@ constexpr int kMaxPower = 32;  // powers are at most floor(lg n) + 1 <= 32 for n
 // Merge-pass keys: node powers, or peeksort depth + 1.  A peeksort node at
 // depth d >= 2 covers at most half the elements of its ancestor at depth
 // d - 2, so internal nodes sit at depth <= 2 floor(lg n) - 1 and their keys
-// are <= 2 floor(lg n) <= 62 for n < 2^31; they fit the fused kernel's
-// 64-bit level mask.
+// are <= 2 floor(lg n) <= 62 for n < 2^31: the per-pass counters hold
+// kMaxPass + 1 entries, and a fused subtree's 64-bit level mask covers them.
 constexpr int kMaxPass = 64;
 
 // Per-call limits.

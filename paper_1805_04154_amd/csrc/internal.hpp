@@ -130,6 +130,7 @@ struct PartitionArgs {
     uint32_t* starts;
     uint32_t* r_dev;
     uint32_t rmax;  // capacity of the leaf arrays
+    uint32_t* samp; // 4-byte keys of a sort that moves data: the sample array to fill (else null)
 };
 
 struct MoveArgs {
@@ -152,10 +153,10 @@ struct MoveArgs {
     SplitRec* split;
     TileSpan* span;            // split_cap entries, beside split
     uint32_t split_cap;        // capacity of split (records)
-    uint32_t fuse_max_leaves;  // leaves a fused subtree can hold at this w
     uint32_t merge_tile;       // outputs per merge-path tile
     uint32_t leaf_copy;        // array that copied long leaves go to (leaf_copy_buf)
     uint32_t n;                // elements of the call
+    uint32_t* samp;            // 4-byte keys: order key of every position divisible by kSampleSpacing (else null)
 };
 
 // Launch shape chosen by the caller (ps_set_tuning) or the defaults.
@@ -163,7 +164,7 @@ struct Tuning {
     uint32_t grid_big_leaf = 2048;
     uint32_t grid_fused = 2048;
     uint32_t grid_merge = 2048;
-    uint32_t grid_split = 512;
+    uint32_t grid_split = 2048;
     uint32_t merge_tile = kMergeTileDefault;
     uint32_t merge_levels = 1;  // 1: one tree level per pass; 2: two-level passes (4-byte keys)
 };

@@ -27,7 +27,6 @@
 
 namespace ps {
 
-constexpr uint32_t kNoneM = 0xFFFFFFFFu;
 
 // Data array b (0, 1, 2) of a MoveArgs pointer triple.
 template <class T>
@@ -48,6 +47,21 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* __restrict__
     }
     return lo;
 }
+
+// The sample array (4-byte keys; null otherwise) keeps the order key of
+// every position divisible by kSampleSpacing: each kernel that changes the
+// data at a position also updates its entry.
+template <class U>
+__device__ __forceinline__ void put_sample(uint32_t* samp, uint32_t pos, U key) {
+    if constexpr (sizeof(U) == 4) {
+        if (samp && (pos & (kSampleSpacing - 1)) == 0) samp[pos / kSampleSpacing] = (uint32_t)key;
+    }
+}
+
+// Padded LDS index: one pad word after every eight, so that a thread
+// handling eight consecutive elements (lane L at 8 L + i) hits a different
+// bank from every other lane (9 L + i).
+__device__ __forceinline__ uint32_t lpad(uint32_t x) { return x + (x >> 3); }
 
 // ------------------------------------------------------------ big leaves
 
@@ -90,6 +104,8 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
                     if (x < x1) {
                         k0[s + x] = ky[j];
                         k0[s + L - 1 - x] = kx[j];
+                        put_sample(a.samp, s + x, Key<KT>::ord(ky[j]));
+                        put_sample(a.samp, s + L - 1 - x, Key<KT>::ord(kx[j]));
                         if (HP) {
                             a.pay[0][s + x] = py[j];
                             a.pay[0][s + L - 1 - x] = px[j];
@@ -117,6 +133,7 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
                     if (x < x1) {
                         const uint32_t y = rev ? (L - 1 - x) : x;
                         k1[s + y] = kv[j];
+                        if (rev) put_sample(a.samp, s + y, Key<KT>::ord(kv[j]));
                         if (HP) p1[s + y] = pv[j];
                     }
                 }
@@ -126,33 +143,6 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
 }
 
 // ------------------------------------------------------- fused subtrees
-
-// Shared-memory layout (dynamic, sized from the largest number of leaves a
-// subtree of kFuse elements can hold, which depends on w).
-struct FuseLayout {
-    uint32_t sk, sp, lst, nlo, nhi, lvl, npw, bytes;
-};
-__host__ __device__ inline FuseLayout fuse_layout(uint32_t key_bytes, bool hp, uint32_t max_leaves) {
-    FuseLayout L;
-    uint32_t at = 128;  // wave totals and the power mask
-    L.sk = at;
-    at += kFuse * key_bytes;
-    L.sp = at;
-    at += hp ? kFuse * 4 : 0;
-
-    L.lst = at;
-    at += (max_leaves + 1) * 2;
-    L.nlo = at;
-    at += max_leaves * 2;
-    L.nhi = at;
-    at += max_leaves * 2;
-    L.lvl = at;
-    at += max_leaves * 2;
-    L.npw = at;
-    at += max_leaves;
-    L.bytes = (at + 15) & ~15u;
-    return L;
-}
 
 // Stable LSD radix sort of the n <= kFuse order keys sk[0..n) (payload sp
 // alongside) held in LDS, 8 bits per pass, ping-ponging with tk/tp; passes
@@ -311,16 +301,13 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
             if (x < n) {
                 dst[lo + x] = K::unord(ok[x]);
                 if (HP) pdst[lo + x] = op[x];
+                put_sample(a.samp, lo + x, ok[x]);
             }
         }
         __syncthreads();
     }
 }
 
-// At most 80 VGPRs (6 waves per SIMD: three 512-thread blocks per CU, whose
-// LDS also fits) at the price of a 32-byte spill: the kernel waits on
-// latency, and the third block hides more of it (4096 random-runs segments
-// of 2^10..2^22 keys: 20.6 -> 16.9 ms).
 // A fused unit that is a single natural run (longer than any min-run
 // extension): copied to its array, reversed if strictly decreasing, without
 // LDS.  Every element is loaded before any is stored, since a run that is a
@@ -359,6 +346,7 @@ __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
                     const uint32_t y = desc ? n - 1 - x : x;
                     dst[lo + y] = kv[i];
                     if (HP) pdst[lo + y] = pv[i];
+                    if (desc) put_sample(a.samp, lo + y, K::ord(kv[i]));
                 }
             }
         }
@@ -366,38 +354,42 @@ __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
     }
 }
 
+// Fused subtrees of fewer than kFuseRadixMinLeaves leaves (so at most six
+// merges), and single leaves of at most kMaxMinRun elements: one block per
+// subtree, its data in LDS.  Leaves are formed first (R1), then the merges
+// run level by level, one level per distinct node power, deepest first
+// (nodes of one power are disjoint, and children have larger powers).
+// Every thread produces the 8 consecutive outputs x0 .. x0 + 7 of a level:
+// each node of that power covering some of them contributes a merge-path
+// co-rank and up to 8 merge steps, the rest are copied.  The node table is
+// block-uniform and small (read from LDS by every lane), so a level costs two
+// barriers.  LDS indices are padded (lpad), so that lanes reading their
+// 8-apart outputs hit different banks.
 template <int KT, bool HP>
 __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6))) void fused_kernel(MoveArgs a) {
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
-    extern __shared__ __align__(16) unsigned char fsm[];
-    const uint32_t ML = a.fuse_max_leaves;
-    const FuseLayout FL = fuse_layout(sizeof(U), HP, ML);
-    uint32_t* sh = reinterpret_cast<uint32_t*>(fsm);
-    unsigned long long* pmask = reinterpret_cast<unsigned long long*>(fsm + 64);
-    U* sk = reinterpret_cast<U*>(fsm + FL.sk);
-    uint32_t* sp = reinterpret_cast<uint32_t*>(fsm + FL.sp);
-    uint16_t* lst = reinterpret_cast<uint16_t*>(fsm + FL.lst);
-    uint16_t* snlo = reinterpret_cast<uint16_t*>(fsm + FL.nlo);
-    uint16_t* snhi = reinterpret_cast<uint16_t*>(fsm + FL.nhi);
-    uint16_t* lvl = reinterpret_cast<uint16_t*>(fsm + FL.lvl);
-    uint8_t* npw = fsm + FL.npw;
-
+    constexpr uint32_t KL = kFuseRadixMinLeaves;  // leaves per subtree stay below this
+    constexpr uint32_t KN = KL - 2;               // merges per subtree: at most KL - 2
+    constexpr uint32_t PADDED = kFuse + kFuse / 8;
+    __shared__ U sk[PADDED];
+    __shared__ uint32_t sp[HP ? PADDED : 1];
+    __shared__ uint32_t lst[KL + 1];
+    __shared__ uint32_t snode[KN][3];  // per merge: first leaf, end leaf, power
     const uint32_t nunits = a.cnt->nunits;
-    const int tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const raw* src = (const raw*)a.keys[0];
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
     for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
         const UnitRec ur = a.unit_rec[u];
-        const uint32_t ua = ur.ua, ub = ur.ub;
-        const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
-        const uint32_t nleaves = ub - ua, nnodes = nleaves - 1;
-        if (n > (uint32_t)kFuse || nleaves == 0 || nleaves > ML) continue;
-        if (fuse_by_radix(sizeof(U), nleaves)) continue;  // fused_radix_kernel's unit
-        if (nleaves == 1 && n > (uint32_t)kMaxMinRun) continue;  // unit_copy_kernel's unit
-        const raw* src = (const raw*)a.keys[0];
+        const uint32_t ua = uni(ur.ua), nl = uni(ur.ub - ur.ua);
+        const uint32_t lo = uni(ur.lo), n = uni(ur.hi - ur.lo);
+        if (n > (uint32_t)kFuse || nl == 0 || fuse_by_radix(sizeof(U), nl)) continue;
+        if (nl == 1 && n > (uint32_t)kMaxMinRun) continue;  // unit_copy_kernel's unit
+        const uint32_t nn = nl - 1;
         raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
         uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
-        if (tid == 0) *pmask = 0;
         U kr[kFuseItems];
         uint32_t pr[kFuseItems];
         {
@@ -410,159 +402,124 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
                     if (HP) pr[i] = a.pay[0][lo + x];
                 }
             }
-            for (uint32_t k = tid; k <= nleaves; k += kFuseThreads) lst[k] = (uint16_t)(a.starts[ua + k] - lo);
+            const uint32_t st = tid <= nl ? a.starts[ua + tid] - lo : 0u;
+            uint32_t nf = 0, ne = 0, np = 0;
+            if (tid < nn) {
+                const uint32_t j = ua + 1 + tid;
+                np = a.P[j];
+                nf = a.Lf[j] - ua;
+                ne = a.Rt[j] - ua;
+            }
+            __syncthreads();  // the previous subtree's last reads are done
+            if (tid <= nl) lst[tid] = st;
+            if (tid < nn) {
+                snode[tid][0] = nf;
+                snode[tid][1] = ne;
+                snode[tid][2] = np;
+            }
 #pragma unroll
             for (int i = 0; i < kFuseItems; ++i) {
                 const uint32_t x = tid + i * kFuseThreads;
                 if (x < n) {
-                    sk[x] = K::ord(kv[i]);
-                    if (HP) sp[x] = pr[i];
+                    sk[lpad(x)] = K::ord(kv[i]);
+                    if (HP) sp[lpad(x)] = pr[i];
                 }
             }
         }
         __syncthreads();
+        // Powers present among the merges.
         unsigned long long pm = 0;
-        for (uint32_t m = tid; m < nnodes; m += kFuseThreads) {
-            const uint32_t j = ua + 1 + m;
-            const uint32_t p = a.P[j];
-            npw[m] = (uint8_t)p;
-            snlo[m] = lst[a.Lf[j] - ua];
-            snhi[m] = lst[a.Rt[j] - ua];
-            pm |= 1ull << p;
-        }
-        if (pm) atomicOr(pmask, pm);
+        for (uint32_t m = 0; m < nn; ++m) pm |= 1ull << uni(snode[m][2]);
 
         // Leaf formation: each leaf is stably sorted in place.
-        uint16_t np[kFuseItems];
         const uint32_t x0 = tid * kFuseItems;
-        // leaf of x0 (lst[l] <= x0 < lst[l+1]); the thread's later elements
-        // advance from it
-        uint32_t l = 0;
+        uint16_t np[kFuseItems];
+        bool moved = false;
         {
-            uint32_t h = nleaves;
-            while (l + 1 < h) {
-                const uint32_t mm = (l + h) >> 1;
-                if (lst[mm] <= x0) l = mm; else h = mm;
-            }
-        }
+            uint32_t l = 0;
+            while (l + 1 < nl && lst[l + 1] <= x0) ++l;
 #pragma unroll
-        for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = x0 + i;
-            np[i] = 0;
-            if (x < n) {
-                while (lst[l + 1] <= x) ++l;
-                const uint32_t ls = lst[l], le = lst[l + 1];
-                const U key = sk[x];
-                uint32_t dpos;
-                if (le - ls <= (uint32_t)kMaxMinRun) {
-                    uint32_t rank = 0;
-                    for (uint32_t y = ls; y < le; ++y) {
-                        const U o = sk[y];
-                        rank += (o < key) || (o == key && y < x);
+            for (int i = 0; i < kFuseItems; ++i) {
+                const uint32_t x = x0 + i;
+                np[i] = (uint16_t)x;
+                if (x < n) {
+                    while (lst[l + 1] <= x) ++l;
+                    const uint32_t ls = lst[l], le = lst[l + 1];
+                    const U key = sk[lpad(x)];
+                    uint32_t dpos;
+                    if (le - ls <= (uint32_t)kMaxMinRun) {
+                        uint32_t rank = 0;
+                        for (uint32_t y = ls; y < le; ++y) {
+                            const U o = sk[lpad(y)];
+                            rank += (o < key) || (o == key && y < x);
+                        }
+                        dpos = ls + rank;
+                    } else {
+                        // longer than any min-run extension: a natural run
+                        const bool desc = sk[lpad(ls + 1)] < sk[lpad(ls)];
+                        dpos = desc ? (ls + le - 1 - x) : x;
                     }
-                    dpos = ls + rank;
-                } else {
-                    // A leaf longer than any min-run extension is a natural run.
-                    const bool desc = sk[ls + 1] < sk[ls];
-                    dpos = desc ? (ls + le - 1 - x) : x;
+                    kr[i] = key;
+                    if (HP) pr[i] = sp[lpad(x)];
+                    np[i] = (uint16_t)dpos;
+                    moved |= (dpos != x);
                 }
-                kr[i] = key;
-                if (HP) pr[i] = sp[x];
-                np[i] = (uint16_t)dpos;
             }
         }
-        __syncthreads();
+        if (__syncthreads_or(moved)) {
 #pragma unroll
-        for (int i = 0; i < kFuseItems; ++i) {
-            if (x0 + i < n) {
-                sk[np[i]] = kr[i];
-                if (HP) sp[np[i]] = pr[i];
-            }
-        }
-        __syncthreads();
-
-        // Internal merges, deepest power first; nodes of one power are disjoint.
-        unsigned long long rem = *pmask;
-        while (rem) {
-            const uint32_t p = 63 - __clzll(rem);
-            rem &= ~(1ull << p);
-            // Nodes of power p in position order.
-            uint32_t nl = 0;
-            for (uint32_t c0 = 0; c0 < nnodes; c0 += kFuseThreads) {
-                const uint32_t m = c0 + tid;
-                const bool f = (m < nnodes) && npw[m] == p;
-                uint32_t tot;
-                const uint32_t pos = block_excl_sum_w<kFuseWaves>(f ? 1u : 0u, sh, &tot);
-                if (f) lvl[nl + pos] = (uint16_t)m;
-                nl += tot;
+            for (int i = 0; i < kFuseItems; ++i) {
+                if (x0 + i < n) {
+                    sk[lpad(np[i])] = kr[i];
+                    if (HP) sp[lpad(np[i])] = pr[i];
+                }
             }
             __syncthreads();
-            // First node whose range ends after x0.
-            uint32_t idx;
-            {
-                uint32_t l = 0, h = nl;
-                while (l < h) {
-                    const uint32_t mm = (l + h) >> 1;
-                    if (snhi[lvl[mm]] <= x0) l = mm + 1; else h = mm;
-                }
-                idx = l;
-            }
-            bool in_node = false;
-            uint32_t ia = 0, ib = 0, ea = 0, eb = 0;
-            uint32_t next_lo = kNoneM;
-            if (idx < nl) {
-                const uint32_t m = lvl[idx];
-                const uint32_t nlo = snlo[m], nmid = lst[m + 1], nhi = snhi[m];
-                if (nlo <= x0 && x0 < n) {
-                    // Merge-path co-rank of diagonal x0 - nlo (ties to the left run).
-                    const uint32_t d = x0 - nlo, la = nmid - nlo, lb = nhi - nmid;
+        }
+
+        // Merges, deepest power first.
+        while (pm) {
+            const uint32_t p = 63 - __clzll(pm);
+            pm &= ~(1ull << p);
+#pragma unroll
+            for (int i = 0; i < kFuseItems; ++i) np[i] = (uint16_t)(x0 + i);  // copied unless merged
+            for (uint32_t m = 0; m < nn; ++m) {
+                if (uni(snode[m][2]) != p) continue;
+                // merge [nlo, nmid) with [nmid, nhi)
+                const uint32_t nlo = uni(lst[snode[m][0]]), nmid = uni(lst[m + 1]), nhi = uni(lst[snode[m][1]]);
+                if (nlo < x0 + kFuseItems && x0 < nhi) {
+                    const uint32_t s0 = max(x0, nlo);
+                    // merge-path co-rank of diagonal s0 - nlo (ties to the left run)
+                    const uint32_t d = s0 - nlo, la = nmid - nlo, lb = nhi - nmid;
                     uint32_t l = d > lb ? d - lb : 0, h = min(d, la);
                     while (l < h) {
                         const uint32_t mm = (l + h) >> 1;
-                        if (sk[nlo + mm] <= sk[nmid + d - 1 - mm]) l = mm + 1; else h = mm;
+                        if (sk[lpad(nlo + mm)] <= sk[lpad(nmid + d - 1 - mm)]) l = mm + 1; else h = mm;
                     }
-                    ia = nlo + l;
-                    ib = nmid + (d - l);
-                    ea = nmid;
-                    eb = nhi;
-                    in_node = true;
-                } else {
-                    next_lo = nlo;
+                    uint32_t ia = nlo + l, ib = nmid + (d - l);
+#pragma unroll
+                    for (int i = 0; i < kFuseItems; ++i) {
+                        const uint32_t x = x0 + i;
+                        if (x >= s0 && x < nhi) {
+                            const bool take_a = (ib >= nhi) || (ia < nmid && sk[lpad(ia)] <= sk[lpad(ib)]);
+                            np[i] = (uint16_t)(take_a ? ia++ : ib++);
+                        }
+                    }
                 }
             }
 #pragma unroll
             for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = x0 + i;
-                if (x < n) {
-                    if (!in_node && x == next_lo) {
-                        const uint32_t m = lvl[idx];
-                        ia = next_lo;
-                        ib = ea = lst[m + 1];
-                        eb = snhi[m];
-                        in_node = true;
-                    }
-                    uint32_t srcpos;
-                    if (in_node) {
-                        const bool take_a = (ib >= eb) || (ia < ea && sk[ia] <= sk[ib]);
-                        srcpos = take_a ? ia++ : ib++;
-                        if (x + 1 == eb) {
-                            in_node = false;
-                            ++idx;
-                            next_lo = (idx < nl) ? snlo[lvl[idx]] : kNoneM;
-                        }
-                    } else {
-                        srcpos = x;
-                    }
-                    kr[i] = sk[srcpos];
-                    if (HP) pr[i] = sp[srcpos];
+                if (x0 + i < n) {
+                    kr[i] = sk[lpad(np[i])];
+                    if (HP) pr[i] = sp[lpad(np[i])];
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < kFuseItems; ++i) {
                 if (x0 + i < n) {
-                    sk[x0 + i] = kr[i];
-                    if (HP) sp[x0 + i] = pr[i];
+                    sk[lpad(x0 + i)] = kr[i];
+                    if (HP) sp[lpad(x0 + i)] = pr[i];
                 }
             }
             __syncthreads();
@@ -571,19 +528,12 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         for (int i = 0; i < kFuseItems; ++i) {
             const uint32_t x = tid + i * kFuseThreads;
             if (x < n) {
-                kr[i] = sk[x];
-                if (HP) pr[i] = sp[x];
+                const U key = sk[lpad(x)];
+                dst[lo + x] = K::unord(key);
+                if (HP) pdst[lo + x] = sp[lpad(x)];
+                put_sample(a.samp, lo + x, key);
             }
         }
-#pragma unroll
-        for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = tid + i * kFuseThreads;
-            if (x < n) {
-                dst[lo + x] = K::unord(kr[i]);
-                if (HP) pdst[lo + x] = pr[i];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -595,10 +545,18 @@ struct MergeShared {
     U sk[TILE];
     uint32_t sp[TILE];
 };
-// LDS of the 4-byte-key merge passes: one pad word after every eight, so
-// that a thread writing its eight consecutive merge outputs (lane L at
-// 8 L + i) hits a different bank from every other lane (9 L + i).
-__device__ __forceinline__ uint32_t lpad(uint32_t x) { return x + (x >> 3); }
+// LDS of the 4-byte-key merge passes, padded (lpad).
+// Sample entries of a merged range [out0, out0 + nt) whose order keys are in
+// padded LDS: one thread per sampled position (nt / kSampleSpacing + 1 must
+// not exceed the block).
+template <class U>
+__device__ __forceinline__ void put_samples_lds(uint32_t* samp, const U* sk, uint32_t out0, uint32_t nt) {
+    if constexpr (sizeof(U) == 4) {
+        if (!samp) return;
+        const uint32_t q = ((out0 + kSampleSpacing - 1) / kSampleSpacing + threadIdx.x) * kSampleSpacing;
+        if (q < out0 + nt) samp[q / kSampleSpacing] = (uint32_t)sk[lpad(q - out0)];
+    }
+}
 template <int KT, int TILE>
 struct MergeSharedPad {
     using U = typename Key<KT>::ukey;
@@ -641,29 +599,157 @@ __device__ __forceinline__ uint32_t corank(const typename Key<KT>::raw* __restri
     return l;
 }
 
-// Split pass: where every merge tile of pass p starts, one thread per tile.
-//  * A node with two inputs A = [lo, mid) and C = [mid, hi) has tiles of
-//    merge_tile outputs: the tile starting at output d takes the co-rank of
-//    diagonal d (A elements among the first d outputs, A first on equal keys).
-//  * A node with an absorbed child merges the left child L = A + B with the
-//    right child R = C + D, neither written out.  Its tile starts are the
-//    node's start and "splitters" every g = kQuadSpacing positions along L
-//    and along R: splitter i of L is its element L[i] (found by the co-rank
-//    of i in A, B), and it starts where the R elements below its key end
-//    (L goes first on equal keys); splitter j of R is R[j], preceded by the
-//    L elements not above its key.  Consecutive starts are at most g apart
-//    in L and in R, so a tile holds at most 2g outputs (the merge pass packs
-//    consecutive tiles into groups of up to kQuadTile).  Their
-//    order in the result has a closed form: R's splitter m g precedes L's
-//    element L[i] exactly when m g < (R elements before L[i]), and vice
-//    versa, so each splitter's tile index is its own index plus the number
-//    of the other child's splitters before it.
-// All tiles of the pass search at once; their first levels share cache lines.
-// Each boundary writes the start of its tile and the end of the previous
-// one (the last boundary of a node also ends its tile at the node's end), so
-// a merge tile is read as one record.
+// k-ary search by the kSplitGroup lanes of an aligned lane group: the first
+// i in [l, h) with pred(i), or h if there is none, for a predicate that is
+// false and then true on [l, h).  Every lane of the group calls it with the
+// same l and h and gets the same result.  Each round, lane j probes the point
+// l + j step, which narrows the range to below step = ceil((h - l) / G): a
+// dependent chain of log_G instead of log_2 loads.
+template <class Pred>
+__device__ __forceinline__ uint32_t group_first(uint32_t l, uint32_t h, Pred pred) {
+    constexpr uint32_t G = kSplitGroup;
+    static_assert(G >= 2 && G < 64 && (G & (G - 1)) == 0, "lane groups split a wave");
+    const uint32_t lane = __lane_id();
+    const uint32_t gl = lane & (G - 1), g0 = lane & ~(G - 1);
+    while (l < h) {
+        const uint32_t step = (h - l + G - 1) / G;
+        const uint32_t q = l + gl * step;
+        const bool t = q >= h || pred(q);
+        const uint64_t m = ((uint64_t)__ballot(t) >> g0) & ((1ull << G) - 1ull);
+        if (m == 0) {
+            l += (G - 1) * step + 1;  // every probe is below h and false
+        } else {
+            const uint32_t f = (uint32_t)__builtin_ctzll(m);
+            if (f == 0) {
+                h = l;
+            } else {
+                const uint32_t nl = l + (f - 1) * step + 1;
+                h = min(l + f * step, h);
+                l = nl;
+            }
+        }
+    }
+    return l;
+}
+
+// Split passes: where every merge tile of pass p starts.  Each boundary
+// writes the start of its tile and the end of the previous one (the last
+// boundary of a node also ends its tile at the node's end), so a merge tile
+// is read as one record.
+__device__ __forceinline__ void write_split(const MoveArgs& a, const NodeRec& R, uint32_t at, uint32_t idx,
+                                            uint32_t last, uint32_t ca, uint32_t cb, uint32_t cc, uint32_t cd) {
+    const uint32_t pa = R.lo + ca, pb = R.m1 + cb, pc = R.mid + cc, pd = R.m2 + cd;
+    const uint32_t out = R.lo + ca + cb + cc + cd;
+    if (at < a.split_cap) {
+        SplitRec& r = a.split[at];
+        r.s[0] = pa;
+        r.s[1] = pb;
+        r.s[2] = pc;
+        r.s[3] = pd;
+        r.out = out;
+        r.bufs = R.bufs;
+        a.span[at].start = out | (idx == 0 ? kFirstTile : 0u);
+        if (idx == last) {
+            r.e[0] = R.m1;
+            r.e[1] = R.mid;
+            r.e[2] = R.m2;
+            r.e[3] = R.hi;
+            a.span[at].end = R.hi;
+        }
+    }
+    if (idx > 0 && at - 1 < a.split_cap) {
+        SplitRec& q = a.split[at - 1];
+        q.e[0] = pa;
+        q.e[1] = pb;
+        q.e[2] = pc;
+        q.e[3] = pd;
+        a.span[at - 1].end = out;
+    }
+}
+
+// Nodes with two inputs A = [lo, mid) and C = [mid, hi) (the pass's tiles
+// [0, ptq)), one group of kSplitGroup lanes per tile.  The tile starting at
+// output d takes the co-rank of diagonal d (A elements among the first d
+// outputs, A first on equal keys).  The search starts in the sample: with
+// S = kSampleSpacing, the sampled elements of A and C (positions divisible
+// by S) keep their relative order in the merge, so the sampled elements
+// among the first d outputs are the first D of the merge of the two samples,
+// where D is one of the two integers next to (d - rA - rC) / S (rA, rC:
+// offsets of the first sampled position in A and C).  The samples' co-ranks
+// at those two diagonals bound the number of sampled A elements before the
+// split, and with it the co-rank, to fewer than 2 S positions; a search
+// there ends it.
 template <int KT>
 __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p) {
+    using K = Key<KT>;
+    using raw = typename K::raw;
+    using U = typename K::ukey;
+    static_assert(sizeof(U) == 4, "the split pass serves 4-byte keys");
+    constexpr uint32_t G = kSplitGroup, S = kSampleSpacing;
+    const uint32_t ntiles = a.cnt->ptq[p];
+    const uint32_t nb = a.cnt->pcount[p];
+    const uint32_t bbase = a.cnt->pbase[p];
+    const uint32_t sb = a.cnt->sbase[p];
+    if (nb == 0) return;
+    const uint32_t* __restrict__ smp = a.samp;
+    const uint32_t* bt = a.bucket_tile + bbase;
+    const uint32_t ngroups = gridDim.x * (kThreads / G);
+    for (uint32_t t = (blockIdx.x * kThreads + threadIdx.x) / G; t < ntiles; t += ngroups) {
+        const uint32_t k = group_first(0, nb, [&](uint32_t i) { return bt[i] > t; }) - 1;
+        const uint32_t node = bbase + k;
+        const NodeRec R = a.node_rec[node];
+        const uint32_t first = a.bucket_tile[node];
+        const uint32_t u = t - first;
+        const raw* A = (const raw*)pick3(a.keys, (R.bufs >> 2) & 3u) + R.lo;
+        const raw* C = (const raw*)pick3(a.keys, (R.bufs >> 6) & 3u) + R.mid;
+        const uint32_t na = R.mid - R.lo, nc = R.hi - R.mid;
+        const uint32_t d = u * a.merge_tile;
+        // samples of A: indices [ja, jc) of smp; of C: [jc, je)
+        const uint32_t ja = (R.lo + S - 1) / S, jc = (R.mid + S - 1) / S, je = (R.hi + S - 1) / S;
+        const uint32_t KA = jc - ja, KC = je - jc;
+        const uint32_t rA = ja * S - R.lo, rC = jc * S - R.mid;
+        const int64_t E = (int64_t)d - rA - rC;  // > -2 S
+        const int64_t D0 = E >= 0 ? (E + S - 1) / S : -((-E) / S);
+        const uint32_t Dc = (uint32_t)min<int64_t>(max<int64_t>(D0, 0), (int64_t)(KA + KC));
+        const uint32_t k0 = group_first(Dc > KC ? Dc - KC : 0u, min(Dc, KA),
+                                        [&](uint32_t i) { return smp[ja + i] > smp[jc + Dc - 1 - i]; });
+        uint32_t k1;  // the samples' co-rank at D0 + 1 (clamped)
+        if (D0 < 0) {
+            k1 = 0;
+        } else if (D0 >= (int64_t)(KA + KC)) {
+            k1 = KA;
+        } else {
+            const uint32_t m0 = Dc - k0;
+            const bool take_a = k0 < KA && (m0 >= KC || smp[ja + k0] <= smp[jc + m0]);
+            k1 = k0 + (take_a ? 1u : 0u);
+        }
+        // k0 <= (sampled A elements before the split) <= k1
+        uint32_t l = k0 == 0 ? 0u : rA + (k0 - 1) * S + 1;
+        uint32_t h = k1 >= KA ? na : rA + k1 * S;
+        l = max(l, d > nc ? d - nc : 0u);
+        h = min(h, min(d, na));
+        const uint32_t ca = group_first(l, h, [&](uint32_t i) { return K::ord(A[i]) > K::ord(C[d - 1 - i]); });
+        if ((threadIdx.x & (G - 1)) == 0)
+            write_split(a, R, sb + first + u, u, (R.hi - R.lo - 1) / a.merge_tile, ca, 0, d - ca, 0);
+    }
+}
+
+// Nodes with an absorbed child (two-level passes; the pass's tiles
+// [ptq, ptiles)), one thread per tile.  Such a node merges the left child
+// L = A + B with the right child R = C + D, neither written out.  Its tile
+// starts are the node's start and "splitters" every g = kQuadSpacing
+// positions along L and along R: splitter i of L is its element L[i] (found
+// by the co-rank of i in A, B), and it starts where the R elements below its
+// key end (L goes first on equal keys); splitter j of R is R[j], preceded by
+// the L elements not above its key.  Consecutive starts are at most g apart
+// in L and in R, so a tile holds at most 2g outputs (the merge pass packs
+// consecutive tiles into groups of up to kQuadTile).  Their order in the
+// result has a closed form: R's splitter m g precedes L's element L[i]
+// exactly when m g < (R elements before L[i]), and vice versa, so each
+// splitter's tile index is its own index plus the number of the other
+// child's splitters before it.
+template <int KT>
+__global__ __launch_bounds__(kThreads) void split_quad_kernel(MoveArgs a, uint32_t p) {
     using K = Key<KT>;
     using raw = typename K::raw;
     using U = typename K::ukey;
@@ -673,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
     const uint32_t sb = a.cnt->sbase[p];
     if (nb == 0) return;
     const uint32_t g = kQuadSpacing;
-    for (uint32_t t = blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
+    for (uint32_t t = a.cnt->ptq[p] + blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
         const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
         const uint32_t node = bbase + k;
         const NodeRec R = a.node_rec[node];
@@ -684,69 +770,33 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
         const raw* C = (const raw*)pick3(a.keys, (R.bufs >> 6) & 3u) + R.mid;
         const raw* D = (const raw*)pick3(a.keys, (R.bufs >> 8) & 3u) + R.m2;
         const uint32_t na = R.m1 - R.lo, nbb = R.mid - R.m1, nc = R.m2 - R.mid, nd = R.hi - R.m2;
-        uint32_t idx = u, last;
-        uint32_t ca = 0, cb = 0, cc = 0, cd = 0;  // elements of A, B, C, D before the boundary
-        if (!node_is_quad(R)) {
-            last = (R.hi - R.lo - 1) / a.merge_tile;
-            const uint32_t d = u * a.merge_tile;
-            ca = corank<KT>(A, na, C, nc, d);
-            cc = d - ca;
+        const uint32_t nl = na + nbb, nr = nc + nd;
+        const uint32_t sl = (nl - 1) / g, sr = (nr - 1) / g;  // splitters of L and R
+        uint32_t idx = 0, ca = 0, cb = 0, cc = 0, cd = 0;   // elements of A, B, C, D before the boundary
+        if (u == 0) {
+            idx = 0;
+        } else if (u <= sl) {
+            const uint32_t i = u * g;
+            ca = nbb ? corank<KT>(A, na, B, nbb, i) : i;
+            cb = i - ca;
+            const bool from_a = cb >= nbb || (ca < na && K::ord(A[ca]) <= K::ord(B[cb]));
+            const U v = K::ord(from_a ? A[ca] : B[cb]);
+            cc = lower_count<KT>(C, nc, v);
+            cd = nd ? lower_count<KT>(D, nd, v) : 0u;
+            const uint32_t before = cc + cd;
+            idx = u + min(sr, before ? (before - 1) / g : 0u);
         } else {
-            const uint32_t nl = na + nbb, nr = nc + nd;
-            const uint32_t sl = (nl - 1) / g, sr = (nr - 1) / g;  // splitters of L and R
-            last = sl + sr;
-            if (u == 0) {
-                idx = 0;
-            } else if (u <= sl) {
-                const uint32_t i = u * g;
-                ca = nbb ? corank<KT>(A, na, B, nbb, i) : i;
-                cb = i - ca;
-                const bool from_a = cb >= nbb || (ca < na && K::ord(A[ca]) <= K::ord(B[cb]));
-                const U v = K::ord(from_a ? A[ca] : B[cb]);
-                cc = lower_count<KT>(C, nc, v);
-                cd = nd ? lower_count<KT>(D, nd, v) : 0u;
-                const uint32_t before = cc + cd;
-                idx = u + min(sr, before ? (before - 1) / g : 0u);
-            } else {
-                const uint32_t m = u - sl, j = m * g;
-                cc = nd ? corank<KT>(C, nc, D, nd, j) : j;
-                cd = j - cc;
-                const bool from_c = cd >= nd || (cc < nc && K::ord(C[cc]) <= K::ord(D[cd]));
-                const U v = K::ord(from_c ? C[cc] : D[cd]);
-                ca = upper_count<KT>(A, na, v);
-                cb = nbb ? upper_count<KT>(B, nbb, v) : 0u;
-                const uint32_t before = ca + cb;
-                idx = m + min(sl, before ? (before - 1) / g : 0u);
-            }
+            const uint32_t m = u - sl, j = m * g;
+            cc = nd ? corank<KT>(C, nc, D, nd, j) : j;
+            cd = j - cc;
+            const bool from_c = cd >= nd || (cc < nc && K::ord(C[cc]) <= K::ord(D[cd]));
+            const U v = K::ord(from_c ? C[cc] : D[cd]);
+            ca = upper_count<KT>(A, na, v);
+            cb = nbb ? upper_count<KT>(B, nbb, v) : 0u;
+            const uint32_t before = ca + cb;
+            idx = m + min(sl, before ? (before - 1) / g : 0u);
         }
-        const uint32_t pa = R.lo + ca, pb = R.m1 + cb, pc = R.mid + cc, pd = R.m2 + cd;
-        const uint32_t out = R.lo + ca + cb + cc + cd;
-        const uint32_t at = sb + first + idx;
-        if (at < a.split_cap) {
-            SplitRec& r = a.split[at];
-            r.s[0] = pa;
-            r.s[1] = pb;
-            r.s[2] = pc;
-            r.s[3] = pd;
-            r.out = out;
-            r.bufs = R.bufs;
-            a.span[at].start = out | (idx == 0 ? kFirstTile : 0u);
-            if (idx == last) {
-                r.e[0] = R.m1;
-                r.e[1] = R.mid;
-                r.e[2] = R.m2;
-                r.e[3] = R.hi;
-                a.span[at].end = R.hi;
-            }
-        }
-        if (idx > 0 && at - 1 < a.split_cap) {
-            SplitRec& q = a.split[at - 1];
-            q.e[0] = pa;
-            q.e[1] = pb;
-            q.e[2] = pc;
-            q.e[3] = pd;
-            a.span[at - 1].end = out;
-        }
+        write_split(a, R, sb + first + idx, idx, sl + sr, ca, cb, cc, cd);
     }
 }
 
@@ -1113,6 +1163,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                 if (HP) pdst[x] = pr[i];
             }
         }
+        put_samples_lds(a.samp, sm.sk, out0, nt);
         __syncthreads();
     }
 }
@@ -1220,6 +1271,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                 if (HP) pdst[x] = pr[i];
             }
         }
+        put_samples_lds(a.samp, sm.sk, out0, nt);
         __syncthreads();
     }
 }
@@ -1238,16 +1290,7 @@ template <int KT, bool HP>
 static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st, hipEvent_t ev0,
                            hipEvent_t ev1) {
     if (stage == 0) launch(big_leaf_kernel<KT, HP>, grid, kThreads, 0, st, ev0, ev1, a);
-    else if (stage == 1) {
-        const uint32_t lds = fuse_layout(sizeof(typename Key<KT>::ukey), HP, a.fuse_max_leaves).bytes;
-        static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (gfx950 has 160 KiB)
-        if (!attr_set) {
-            (void)hipFuncSetAttribute((const void*)fused_kernel<KT, HP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      160 * 1024);
-            attr_set = true;
-        }
-        launch(fused_kernel<KT, HP>, grid, kFuseThreads, lds, st, ev0, ev1, a);
-    }
+    else if (stage == 1) launch(fused_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
@@ -1280,13 +1323,17 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         if constexpr (sizeof(typename Key<KT>::ukey) == 4)
             launch(merge_quad_kernel<KT, HP, 512, 8>, grid, 512, 0, st, ev0, ev1, a, p);
     }
-    else launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
+    else if constexpr (sizeof(typename Key<KT>::ukey) == 4) {
+        if (stage == 3) launch(split_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
+        else launch(split_quad_kernel<KT>, grid, kThreads, 0, st, ev0, ev1, a, p);
+    }
 }
 
 // stage 0: big leaves; 5: single-run fused units (copied); 1: fused
 // subtrees (level by level); 4: fused subtrees with many leaves (radix
 // sort); 2: the merge pass of power p; 6: its merges of nodes with an
-// absorbed child; 3: the split pass of power p.
+// absorbed child; 3: the split pass of power p (7: its tiles of nodes with
+// an absorbed child).
 // ev0 / ev1: optional dispatch events.
 hipError_t launch_move_stage(int kt, bool hp, const MoveArgs& a, int stage, uint32_t p, uint32_t grid,
                              hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {

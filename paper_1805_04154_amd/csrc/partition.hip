@@ -33,6 +33,8 @@ namespace ps {
 
 constexpr int kPairItems = 17;                     // pairs per thread in the window scan
 constexpr int kPairCap = kThreads * kPairItems;    // 4352 >= kPartTile + kMaxMinRun + 2
+static_assert(kPartTile % kSampleSpacing == 0 && kPartTile / kSampleSpacing <= kThreads,
+              "a partition tile starts at a sampled position, and one thread stores each of its samples");
 constexpr uint32_t kFar = 0xFFFFFFFEu;             // a position beyond the tile's window (!= kInf)
 constexpr uint16_t kExitBit = 0x8000u;
 // kWalkMax (internal.hpp): a chain never takes more steps in a tile than the
@@ -76,6 +78,7 @@ struct PartShared {
     uint32_t sh[2 * kWaves];
     uint32_t gfirst;
     uint32_t x0;                              // end of the run crossing T0 (kFar / kInf)
+    uint32_t smp[kPartTile / kSampleSpacing]; // order keys of the tile's sampled positions
 };
 
 // Classifies pairs of tile [T0, T1) and its window and sets sm.x0, the end of
@@ -95,7 +98,8 @@ template <int KT>
 __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __restrict__ keys, uint32_t N,
                                 const uint64_t* __restrict__ offsets, uint32_t nseg,
                                 const uint32_t* __restrict__ tile_seg, uint32_t w,
-                                uint32_t T0, uint32_t T1, PartShared<KT>& sm) {
+                                uint32_t T0, uint32_t T1, PartShared<KT>& sm,
+                                uint32_t* __restrict__ samp = nullptr) {
     using K = Key<KT>;
     using U = typename K::ukey;
     const int tid = threadIdx.x;
@@ -115,6 +119,16 @@ __device__ __forceinline__ int tile_successors(const typename Key<KT>::raw* __re
         for (int i = 0; i < kPairItems; ++i) {
             const uint32_t k = tid + i * kThreads;
             if (k < NPW && !(k == 0 && T0 == 0)) kv[i] = keys[T0 - 1 + k];
+        }
+        if (sizeof(U) == 4 && samp) {
+            // the tile's sampled positions (T0 is a multiple of the spacing),
+            // kept in LDS: the caller stores them after its last barrier
+#pragma unroll
+            for (int i = 0; i < kPairItems; ++i) {
+                const uint32_t k = tid + i * kThreads;
+                if (k >= 1 && T0 - 1 + k < T1 && ((k - 1) & (kSampleSpacing - 1)) == 0)
+                    sm.smp[(k - 1) / kSampleSpacing] = (uint32_t)K::ord(kv[i]);
+            }
         }
         if (lane == 0) {
 #pragma unroll
@@ -304,13 +318,21 @@ template <int KT>
 __global__ __launch_bounds__(kThreads) void part_tables_kernel(
     const typename Key<KT>::raw* __restrict__ keys, uint32_t N, const uint64_t* __restrict__ offsets,
     uint32_t nseg, const uint32_t* __restrict__ tile_seg, uint32_t w, uint8_t* __restrict__ tcode,
-    uint32_t* __restrict__ tcnt, TileRec* __restrict__ tile_rec) {
+    uint32_t* __restrict__ tcnt, TileRec* __restrict__ tile_rec, uint32_t* __restrict__ samp) {
     __shared__ PartShared<KT> sm;
     const uint32_t T0 = blockIdx.x * kPartTile;
     const uint32_t T1 = min(N, T0 + kPartTile);
     const uint32_t len = T1 - T0;
     const uint32_t W1 = w + 1;
-    const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm);
+    const int mode = tile_successors<KT>(keys, N, offsets, nseg, tile_seg, w, T0, T1, sm, samp);
+    // The sample's stores wait until no barrier follows (a barrier would wait
+    // for them).
+    auto store_samples = [&]() {
+        if (sizeof(typename Key<KT>::ukey) == 4 && samp) {
+            const uint32_t m = threadIdx.x;
+            if (m < (len + kSampleSpacing - 1) / kSampleSpacing) samp[T0 / kSampleSpacing + m] = sm.smp[m];
+        }
+    };
     {
         // the record the emit pass follows instead of reloading the keys
         TileRec* R = tile_rec + blockIdx.x;
@@ -338,6 +360,7 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
             tcode[(size_t)blockIdx.x * W1 + c] = (uint8_t)w;
             tcnt[(size_t)blockIdx.x * W1 + c] = via_run ? 0u : 1u;
         }
+        store_samples();
         return;
     }
 
@@ -415,6 +438,7 @@ __global__ __launch_bounds__(kThreads) void part_tables_kernel(
         tcode[(size_t)blockIdx.x * W1 + c] = code;
         tcnt[(size_t)blockIdx.x * W1 + c] = cnt;
     }
+    store_samples();
 }
 
 // Up-sweep: compose groups of kScanGroup consecutive tables into one.
@@ -648,7 +672,7 @@ hipError_t launch_partition_t(const PartitionArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(tile_seg_kernel, dim3(std::min<uint32_t>((nT + kThreads - 1) / kThreads, 4096u)),
                            dim3(kThreads), 0, st, a.offsets, a.nseg, nT, a.tile_seg);
     hipLaunchKernelGGL(part_tables_kernel<KT>, dim3(nT), dim3(kThreads), 0, st, (const raw*)a.keys, a.N,
-                       a.offsets, a.nseg, a.tile_seg, a.w, a.code[0], a.cnt[0], a.tile_rec);
+                       a.offsets, a.nseg, a.tile_seg, a.w, a.code[0], a.cnt[0], a.tile_rec, a.samp);
     const size_t lds = (size_t)kScanGroup * W1 * 5;
     for (int l = 0; l + 1 < a.levels; ++l)
         hipLaunchKernelGGL(compose_up_kernel, dim3(a.ntab[l + 1]), dim3(kThreads), lds, st, a.code[l], a.cnt[l],

@@ -130,15 +130,26 @@ def test_no_alloc_entry_point_rejects_before_launch(lib):
     from paper_1805_04154_amd import binding
     fake = ctypes.c_void_p(0x1000)
     cap = 128 << 20
-    # largest n whose scratch fits the fixed 128 MiB array, int32 keys + payload
-    lo, hi = 1, 1 << 31
-    while lo < hi:
-        m = (lo + hi + 1) // 2
-        if lib.ps_workspace_bytes(m, 1, 0, 1, None) <= cap:
-            lo = m
-        else:
-            hi = m - 1
-    assert lo > 6_000_000
+
+    def largest(kt, hp):
+        # largest n whose scratch fits the fixed 128 MiB array
+        lo, hi = 1, 1 << 31
+        while lo < hi:
+            m = (lo + hi + 1) // 2
+            if lib.ps_workspace_bytes(m, 1, kt, hp, None) <= cap:
+                lo = m
+            else:
+                hi = m - 1
+        return lo
+
+    # the limits the header states (int32 / int64 keys, with and without payload)
+    text = " ".join(re.sub(r"^\s*\*", "", line) for line in open(HEADER).read().splitlines())
+    text = " ".join(text.split())
+    m = re.search(r"above ([\d ]+) 4-byte keys with a payload \(([\d ]+) without\) or ([\d ]+) 8-byte keys "
+                  r"with a payload \(([\d ]+) without\)", text)
+    stated = [int(g.replace(" ", "")) for g in m.groups()]
+    assert stated == [largest(0, 1), largest(0, 0), largest(2, 1), largest(2, 0)]
+    lo = stated[0]
     assert lib.ps_sort_no_alloc(fake, fake, lo + 1, 0, None, None, None) == -2
     assert b"fixed scratch" in lib.ps_last_error()
     assert lib.ps_sort_no_alloc(fake, None, 1 << 31, 0, None, None, None) == -2

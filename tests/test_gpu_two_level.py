@@ -128,7 +128,7 @@ def test_merge_tiles(ps, tile):
         ps.set_tuning({"merge_tile": tile, "merge_levels": 2, "grid_merge": 333, "grid_split": 77})
         gk, gp, gm = run_sort(ps, wl.keys, True, False)
     finally:
-        ps.set_tuning({"merge_levels": 2, "merge_tile": 8192, "grid_merge": 2048, "grid_split": 512})
+        ps.set_tuning({"merge_levels": 2, "merge_tile": 8192, "grid_merge": 2048, "grid_split": 2048})
     assert np.array_equal(gk, ref.keys) and np.array_equal(gp, ref.payload) and gm == ref.merge_cost
 
 
