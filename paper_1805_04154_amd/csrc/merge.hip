@@ -354,6 +354,8 @@ __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
     }
 }
 
+constexpr int kFusedNT = 1024;  // threads of fused_kernel (kFuse / kFusedNT outputs each)
+
 // Fused subtrees of fewer than kFuseRadixMinLeaves leaves (so at most six
 // merges), and single leaves of at most kMaxMinRun elements: one block per
 // subtree, its data in LDS.  Leaves are formed first (R1), then the merges
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
 // barriers.  LDS indices are padded (lpad), so that lanes reading their
 // 8-apart outputs hit different banks.
 template <int KT, bool HP>
-__global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6))) void fused_kernel(MoveArgs a) {
+__global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) void fused_kernel(MoveArgs a) {
+    constexpr int NT = kFusedNT, IT = kFuse / kFusedNT;
     using K = Key<KT>;
     using U = typename K::ukey;
     using raw = typename K::raw;
@@ -390,13 +393,13 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         const uint32_t nn = nl - 1;
         raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
         uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
-        U kr[kFuseItems];
-        uint32_t pr[kFuseItems];
+        U kr[IT];
+        uint32_t pr[IT];
         {
-            raw kv[kFuseItems];
+            raw kv[IT];
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = tid + i * kFuseThreads;
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = tid + i * NT;
                 if (x < n) {
                     kv[i] = src[lo + x];
                     if (HP) pr[i] = a.pay[0][lo + x];
@@ -418,8 +421,8 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
                 snode[tid][2] = np;
             }
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = tid + i * kFuseThreads;
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = tid + i * NT;
                 if (x < n) {
                     sk[lpad(x)] = K::ord(kv[i]);
                     if (HP) sp[lpad(x)] = pr[i];
@@ -432,14 +435,14 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         for (uint32_t m = 0; m < nn; ++m) pm |= 1ull << uni(snode[m][2]);
 
         // Leaf formation: each leaf is stably sorted in place.
-        const uint32_t x0 = tid * kFuseItems;
-        uint16_t np[kFuseItems];
+        const uint32_t x0 = tid * IT;
+        uint16_t np[IT];
         bool moved = false;
         {
             uint32_t l = 0;
             while (l + 1 < nl && lst[l + 1] <= x0) ++l;
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 const uint32_t x = x0 + i;
                 np[i] = (uint16_t)x;
                 if (x < n) {
@@ -449,6 +452,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
                     uint32_t dpos;
                     if (le - ls <= (uint32_t)kMaxMinRun) {
                         uint32_t rank = 0;
+#pragma unroll 1
                         for (uint32_t y = ls; y < le; ++y) {
                             const U o = sk[lpad(y)];
                             rank += (o < key) || (o == key && y < x);
@@ -468,7 +472,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
         }
         if (__syncthreads_or(moved)) {
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 if (x0 + i < n) {
                     sk[lpad(np[i])] = kr[i];
                     if (HP) sp[lpad(np[i])] = pr[i];
@@ -482,12 +486,13 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
             const uint32_t p = 63 - __clzll(pm);
             pm &= ~(1ull << p);
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) np[i] = (uint16_t)(x0 + i);  // copied unless merged
+            for (int i = 0; i < IT; ++i) np[i] = (uint16_t)(x0 + i);  // copied unless merged
+#pragma unroll 1
             for (uint32_t m = 0; m < nn; ++m) {
                 if (uni(snode[m][2]) != p) continue;
                 // merge [nlo, nmid) with [nmid, nhi)
                 const uint32_t nlo = uni(lst[snode[m][0]]), nmid = uni(lst[m + 1]), nhi = uni(lst[snode[m][1]]);
-                if (nlo < x0 + kFuseItems && x0 < nhi) {
+                if (nlo < x0 + IT && x0 < nhi) {
                     const uint32_t s0 = max(x0, nlo);
                     // merge-path co-rank of diagonal s0 - nlo (ties to the left run)
                     const uint32_t d = s0 - nlo, la = nmid - nlo, lb = nhi - nmid;
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
                     }
                     uint32_t ia = nlo + l, ib = nmid + (d - l);
 #pragma unroll
-                    for (int i = 0; i < kFuseItems; ++i) {
+                    for (int i = 0; i < IT; ++i) {
                         const uint32_t x = x0 + i;
                         if (x >= s0 && x < nhi) {
                             const bool take_a = (ib >= nhi) || (ia < nmid && sk[lpad(ia)] <= sk[lpad(ib)]);
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
                 }
             }
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 if (x0 + i < n) {
                     kr[i] = sk[lpad(np[i])];
                     if (HP) pr[i] = sp[lpad(np[i])];
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
             }
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
+            for (int i = 0; i < IT; ++i) {
                 if (x0 + i < n) {
                     sk[lpad(x0 + i)] = kr[i];
                     if (HP) sp[lpad(x0 + i)] = pr[i];
@@ -525,8 +530,8 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(6)
             __syncthreads();
         }
 #pragma unroll
-        for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = tid + i * kFuseThreads;
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t x = tid + i * NT;
             if (x < n) {
                 const U key = sk[lpad(x)];
                 dst[lo + x] = K::unord(key);
@@ -1290,7 +1295,7 @@ template <int KT, bool HP>
 static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st, hipEvent_t ev0,
                            hipEvent_t ev1) {
     if (stage == 0) launch(big_leaf_kernel<KT, HP>, grid, kThreads, 0, st, ev0, ev1, a);
-    else if (stage == 1) launch(fused_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
+    else if (stage == 1) launch(fused_kernel<KT, HP>, grid, kFusedNT, 0, st, ev0, ev1, a);
     else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
