@@ -672,31 +672,84 @@ __device__ __forceinline__ void write_split(const MoveArgs& a, const NodeRec& R,
     }
 }
 
+// Searches of the split passes, by the kSplitGroup lanes of a lane group,
+// over runs whose sampled positions (divisible by S = kSampleSpacing) keep
+// their order keys in a.samp.  A run X occupies positions [xs, xe); its
+// samples are smp[j0 .. j1) for the first sampled position j0 S = xs + r.
+//
+// Co-rank of diagonal d in the stable merge of X = [xs, xe) with the run
+// Y = [ys, ye) that follows it (X first on equal keys): the sampled elements
+// of X and Y keep their relative order in the merge, so the sampled
+// elements among its first d outputs are the first D of the merge of the two
+// samples, where D is one of the two integers next to (d - rX - rY) / S.  The
+// samples' co-ranks at those two diagonals bound the number of sampled X
+// elements before the split, and with it the co-rank, to fewer than 2 S
+// positions; a search there ends it.
+template <int KT>
+__device__ __forceinline__ uint32_t group_corank(const uint32_t* __restrict__ smp, const typename Key<KT>::raw* X,
+                                                 uint32_t xs, uint32_t xe, const typename Key<KT>::raw* Y,
+                                                 uint32_t ys, uint32_t ye, uint32_t d) {
+    using K = Key<KT>;
+    constexpr uint32_t S = kSampleSpacing;
+    const uint32_t nx = xe - xs, ny = ye - ys;
+    const uint32_t ja = (xs + S - 1) / S, jc = (ys + S - 1) / S, je = (ye + S - 1) / S;
+    const uint32_t KA = jc - ja, KC = je - jc;  // X's samples end where Y's begin (ys = xe)
+    const uint32_t rA = ja * S - xs, rC = jc * S - ys;
+    const int64_t E = (int64_t)d - rA - rC;  // > -2 S
+    const int64_t D0 = E >= 0 ? (E + S - 1) / S : -((-E) / S);
+    const uint32_t Dc = (uint32_t)min<int64_t>(max<int64_t>(D0, 0), (int64_t)(KA + KC));
+    const uint32_t k0 = group_first(Dc > KC ? Dc - KC : 0u, min(Dc, KA),
+                                    [&](uint32_t i) { return smp[ja + i] > smp[jc + Dc - 1 - i]; });
+    uint32_t k1;  // the samples' co-rank at D0 + 1 (clamped)
+    if (D0 < 0) {
+        k1 = 0;
+    } else if (D0 >= (int64_t)(KA + KC)) {
+        k1 = KA;
+    } else {
+        const uint32_t m0 = Dc - k0;
+        const bool take_x = k0 < KA && (m0 >= KC || smp[ja + k0] <= smp[jc + m0]);
+        k1 = k0 + (take_x ? 1u : 0u);
+    }
+    // k0 <= (sampled X elements before the split) <= k1
+    uint32_t l = k0 == 0 ? 0u : rA + (k0 - 1) * S + 1;
+    uint32_t h = k1 >= KA ? nx : rA + k1 * S;
+    l = max(l, d > ny ? d - ny : 0u);
+    h = min(h, min(d, nx));
+    return group_first(l, h, [&](uint32_t i) { return K::ord(X[i]) > K::ord(Y[d - 1 - i]); });
+}
+
+// Elements of the run X = [xs, xe) whose order key is below v (or not above
+// v, with le): the count of sampled elements that qualify, k, places it
+// after the k-th sample and not after the (k+1)-th, a window of at most S.
+template <int KT>
+__device__ __forceinline__ uint32_t group_count(const uint32_t* __restrict__ smp, const typename Key<KT>::raw* X,
+                                                uint32_t xs, uint32_t xe, uint32_t v, bool le) {
+    using K = Key<KT>;
+    constexpr uint32_t S = kSampleSpacing;
+    const uint32_t nx = xe - xs;
+    const uint32_t j0 = (xs + S - 1) / S, K1 = (xe + S - 1) / S - j0, r = j0 * S - xs;
+    auto fails = [&](uint32_t u) { return le ? u > v : u >= v; };
+    const uint32_t k = group_first(0, K1, [&](uint32_t i) { return fails(smp[j0 + i]); });
+    const uint32_t l = k == 0 ? 0u : r + (k - 1) * S + 1;
+    const uint32_t h = k >= K1 ? nx : r + k * S;
+    return group_first(l, h, [&](uint32_t i) { return fails((uint32_t)K::ord(X[i])); });
+}
+
 // Nodes with two inputs A = [lo, mid) and C = [mid, hi) (the pass's tiles
-// [0, ptq)), one group of kSplitGroup lanes per tile.  The tile starting at
+// [0, ptq)), one group of kSplitGroup lanes per tile: the tile starting at
 // output d takes the co-rank of diagonal d (A elements among the first d
-// outputs, A first on equal keys).  The search starts in the sample: with
-// S = kSampleSpacing, the sampled elements of A and C (positions divisible
-// by S) keep their relative order in the merge, so the sampled elements
-// among the first d outputs are the first D of the merge of the two samples,
-// where D is one of the two integers next to (d - rA - rC) / S (rA, rC:
-// offsets of the first sampled position in A and C).  The samples' co-ranks
-// at those two diagonals bound the number of sampled A elements before the
-// split, and with it the co-rank, to fewer than 2 S positions; a search
-// there ends it.
+// outputs, A first on equal keys).
 template <int KT>
 __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p) {
     using K = Key<KT>;
     using raw = typename K::raw;
-    using U = typename K::ukey;
-    static_assert(sizeof(U) == 4, "the split pass serves 4-byte keys");
-    constexpr uint32_t G = kSplitGroup, S = kSampleSpacing;
+    static_assert(sizeof(typename K::ukey) == 4, "the split pass serves 4-byte keys");
+    constexpr uint32_t G = kSplitGroup;
     const uint32_t ntiles = a.cnt->ptq[p];
     const uint32_t nb = a.cnt->pcount[p];
     const uint32_t bbase = a.cnt->pbase[p];
     const uint32_t sb = a.cnt->sbase[p];
     if (nb == 0) return;
-    const uint32_t* __restrict__ smp = a.samp;
     const uint32_t* bt = a.bucket_tile + bbase;
     const uint32_t ngroups = gridDim.x * (kThreads / G);
     for (uint32_t t = (blockIdx.x * kThreads + threadIdx.x) / G; t < ntiles; t += ngroups) {
@@ -707,40 +760,15 @@ __global__ __launch_bounds__(kThreads) void split_kernel(MoveArgs a, uint32_t p)
         const uint32_t u = t - first;
         const raw* A = (const raw*)pick3(a.keys, (R.bufs >> 2) & 3u) + R.lo;
         const raw* C = (const raw*)pick3(a.keys, (R.bufs >> 6) & 3u) + R.mid;
-        const uint32_t na = R.mid - R.lo, nc = R.hi - R.mid;
         const uint32_t d = u * a.merge_tile;
-        // samples of A: indices [ja, jc) of smp; of C: [jc, je)
-        const uint32_t ja = (R.lo + S - 1) / S, jc = (R.mid + S - 1) / S, je = (R.hi + S - 1) / S;
-        const uint32_t KA = jc - ja, KC = je - jc;
-        const uint32_t rA = ja * S - R.lo, rC = jc * S - R.mid;
-        const int64_t E = (int64_t)d - rA - rC;  // > -2 S
-        const int64_t D0 = E >= 0 ? (E + S - 1) / S : -((-E) / S);
-        const uint32_t Dc = (uint32_t)min<int64_t>(max<int64_t>(D0, 0), (int64_t)(KA + KC));
-        const uint32_t k0 = group_first(Dc > KC ? Dc - KC : 0u, min(Dc, KA),
-                                        [&](uint32_t i) { return smp[ja + i] > smp[jc + Dc - 1 - i]; });
-        uint32_t k1;  // the samples' co-rank at D0 + 1 (clamped)
-        if (D0 < 0) {
-            k1 = 0;
-        } else if (D0 >= (int64_t)(KA + KC)) {
-            k1 = KA;
-        } else {
-            const uint32_t m0 = Dc - k0;
-            const bool take_a = k0 < KA && (m0 >= KC || smp[ja + k0] <= smp[jc + m0]);
-            k1 = k0 + (take_a ? 1u : 0u);
-        }
-        // k0 <= (sampled A elements before the split) <= k1
-        uint32_t l = k0 == 0 ? 0u : rA + (k0 - 1) * S + 1;
-        uint32_t h = k1 >= KA ? na : rA + k1 * S;
-        l = max(l, d > nc ? d - nc : 0u);
-        h = min(h, min(d, na));
-        const uint32_t ca = group_first(l, h, [&](uint32_t i) { return K::ord(A[i]) > K::ord(C[d - 1 - i]); });
+        const uint32_t ca = group_corank<KT>(a.samp, A, R.lo, R.mid, C, R.mid, R.hi, d);
         if ((threadIdx.x & (G - 1)) == 0)
             write_split(a, R, sb + first + u, u, (R.hi - R.lo - 1) / a.merge_tile, ca, 0, d - ca, 0);
     }
 }
 
 // Nodes with an absorbed child (two-level passes; the pass's tiles
-// [ptq, ptiles)), one thread per tile.  Such a node merges the left child
+// [ptq, ptiles)), one lane group per tile.  Such a node merges the left child
 // L = A + B with the right child R = C + D, neither written out.  Its tile
 // starts are the node's start and "splitters" every g = kQuadSpacing
 // positions along L and along R: splitter i of L is its element L[i] (found
@@ -758,14 +786,17 @@ __global__ __launch_bounds__(kThreads) void split_quad_kernel(MoveArgs a, uint32
     using K = Key<KT>;
     using raw = typename K::raw;
     using U = typename K::ukey;
+    constexpr uint32_t G = kSplitGroup;
     const uint32_t ntiles = a.cnt->ptiles[p];
     const uint32_t nb = a.cnt->pcount[p];
     const uint32_t bbase = a.cnt->pbase[p];
     const uint32_t sb = a.cnt->sbase[p];
     if (nb == 0) return;
     const uint32_t g = kQuadSpacing;
-    for (uint32_t t = a.cnt->ptq[p] + blockIdx.x * kThreads + threadIdx.x; t < ntiles; t += gridDim.x * kThreads) {
-        const uint32_t k = upper_bound_u32(a.bucket_tile + bbase, nb, t) - 1;
+    const uint32_t* bt = a.bucket_tile + bbase;
+    const uint32_t ngroups = gridDim.x * (kThreads / G);
+    for (uint32_t t = a.cnt->ptq[p] + (blockIdx.x * kThreads + threadIdx.x) / G; t < ntiles; t += ngroups) {
+        const uint32_t k = group_first(0, nb, [&](uint32_t i) { return bt[i] > t; }) - 1;
         const uint32_t node = bbase + k;
         const NodeRec R = a.node_rec[node];
         const uint32_t first = a.bucket_tile[node];
@@ -782,26 +813,26 @@ __global__ __launch_bounds__(kThreads) void split_quad_kernel(MoveArgs a, uint32
             idx = 0;
         } else if (u <= sl) {
             const uint32_t i = u * g;
-            ca = nbb ? corank<KT>(A, na, B, nbb, i) : i;
+            ca = nbb ? group_corank<KT>(a.samp, A, R.lo, R.m1, B, R.m1, R.mid, i) : i;
             cb = i - ca;
             const bool from_a = cb >= nbb || (ca < na && K::ord(A[ca]) <= K::ord(B[cb]));
             const U v = K::ord(from_a ? A[ca] : B[cb]);
-            cc = lower_count<KT>(C, nc, v);
-            cd = nd ? lower_count<KT>(D, nd, v) : 0u;
+            cc = group_count<KT>(a.samp, C, R.mid, R.m2, v, false);
+            cd = nd ? group_count<KT>(a.samp, D, R.m2, R.hi, v, false) : 0u;
             const uint32_t before = cc + cd;
             idx = u + min(sr, before ? (before - 1) / g : 0u);
         } else {
             const uint32_t m = u - sl, j = m * g;
-            cc = nd ? corank<KT>(C, nc, D, nd, j) : j;
+            cc = nd ? group_corank<KT>(a.samp, C, R.mid, R.m2, D, R.m2, R.hi, j) : j;
             cd = j - cc;
             const bool from_c = cd >= nd || (cc < nc && K::ord(C[cc]) <= K::ord(D[cd]));
             const U v = K::ord(from_c ? C[cc] : D[cd]);
-            ca = upper_count<KT>(A, na, v);
-            cb = nbb ? upper_count<KT>(B, nbb, v) : 0u;
+            ca = group_count<KT>(a.samp, A, R.lo, R.m1, v, true);
+            cb = nbb ? group_count<KT>(a.samp, B, R.m1, R.mid, v, true) : 0u;
             const uint32_t before = ca + cb;
             idx = m + min(sl, before ? (before - 1) / g : 0u);
         }
-        write_split(a, R, sb + first + idx, idx, sl + sr, ca, cb, cc, cd);
+        if ((threadIdx.x & (G - 1)) == 0) write_split(a, R, sb + first + idx, idx, sl + sr, ca, cb, cc, cd);
     }
 }
 
