@@ -87,7 +87,7 @@ constexpr uint32_t kMergeTileMin = 2048;
 // Merges with absorbed children: splitters every kQuadSpacing positions of
 // each child's merge, so a tile holds at most 2 kQuadSpacing outputs, and
 // the merge pass packs consecutive tiles into groups of up to kQuadTile.
-constexpr uint32_t kQuadSpacing = 1024;
+constexpr uint32_t kQuadSpacing = 2048;
 constexpr uint32_t kQuadTile = 4096;
 // Splitter search (4-byte keys): every position divisible by kSampleSpacing
 // keeps a copy of its current order key in a small sample array, so that a
