@@ -83,13 +83,12 @@ TRACE_MD = os.path.join(ROOT, "profiles", "kernels_zipf_2p28_i32.md")
 
 
 def merge_kernel_digest() -> str:
-    """Digest of the merge-pass kernels' source text (their LDS layout and
-    bodies: the two-input and the four-input merge)."""
+    """Digest of the source text of the kernel the roofline measures, the
+    two-input merge pass (its body, its LDS padding and its sample writes)."""
     src = open(os.path.join(ROOT, "paper_1805_04154_amd", "csrc", "merge.hip")).read()
     a = src.index("__device__ __forceinline__ uint32_t lpad(")
     parts = [src[a:src.index("\n", a)]]  # the one-line padding function
-    for start in ("void merge_quad_kernel(MoveArgs a, uint32_t p) {", "void merge_pass_kernel(MoveArgs a, uint32_t p) {",
-                  "void put_samples_lds("):
+    for start in ("void merge_pass_kernel(MoveArgs a, uint32_t p) {", "void put_samples_lds("):
         a = src.index(start)
         parts.append(src[a:src.index("\n}\n", a)])
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]

@@ -89,6 +89,7 @@ constexpr uint32_t kMergeTileMin = 2048;
 // the merge pass packs consecutive tiles into groups of up to kQuadTile.
 constexpr uint32_t kQuadSpacing = 2048;
 constexpr uint32_t kQuadTile = 4096;
+constexpr int kLog2QuadTile = 13;  // halving steps of a co-rank search over up to kQuadTile elements
 // Splitter search (4-byte keys): every position divisible by kSampleSpacing
 // keeps a copy of its current order key in a small sample array, so that a
 // merge-path co-rank is first found among the samples (a few cached lines)

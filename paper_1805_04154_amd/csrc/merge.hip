@@ -569,6 +569,23 @@ struct MergeSharedPad {
     uint32_t sp[TILE + TILE / 8];
 };
 
+// Merge-path co-rank in padded LDS by a fixed number of halving steps (no
+// divergence between lanes): the number of elements of the run
+// sk[xa, xa + n1) among the first d outputs of its stable merge with the run
+// sk[xb, xb + n2) (the first run first on equal keys), for n1 < 2^STEPS.
+template <int STEPS, class U>
+__device__ __forceinline__ uint32_t lds_corank(const U* sk, uint32_t xa, uint32_t n1, uint32_t xb, uint32_t n2,
+                                               uint32_t d) {
+    const uint32_t hi = min(d, n1);
+    uint32_t c = d > n2 ? d - n2 : 0;
+#pragma unroll
+    for (int k = STEPS - 1; k >= 0; --k) {
+        const uint32_t q = c + (1u << k);
+        if (q <= hi && sk[lpad(xa + q - 1)] <= sk[lpad(xb + d - q)]) c = q;
+    }
+    return c;
+}
+
 // Key-order bounds in a sorted run: the number of run elements whose key is
 // below v (lower) or not above v (upper).
 template <int KT>
@@ -1118,11 +1135,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                 const bool right = dx >= nl;
                 const uint32_t base = right ? nl : 0u, n1 = right ? nc : na, n2 = right ? nd : nbp;
                 const uint32_t dg = dx - base;
-                uint32_t l = dg > n2 ? dg - n2 : 0, h = min(dg, n1);
-                while (l < h) {
-                    const uint32_t m = (l + h) >> 1;
-                    if (sm.sk[lpad(base + m)] <= sm.sk[lpad(base + n1 + dg - 1 - m)]) l = m + 1; else h = m;
-                }
+                const uint32_t l = lds_corank<kLog2QuadTile>(sm.sk, base, n1, base + n1, n2, dg);
                 uint32_t i1 = base + l, e1 = base + n1, i2 = base + n1 + (dg - l), e2 = base + n1 + n2;
 #pragma unroll
                 for (int i = 0; i < IT; ++i) {
@@ -1134,10 +1147,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                             i2 = ncl;
                             e2 = nt;
                         }
-                        const bool take1 = (i2 >= e2) || (i1 < e1 && sm.sk[lpad(i1)] <= sm.sk[lpad(i2)]);
-                        const uint32_t s = take1 ? i1++ : i2++;
-                        kr[i] = sm.sk[lpad(s)];
+                        // both heads read (clamped inside the tile), then selected: no branch
+                        const U k1 = sm.sk[lpad(min(i1, nt - 1))], k2 = sm.sk[lpad(min(i2, nt - 1))];
+                        const bool take1 = (i2 >= e2) | ((i1 < e1) & (k1 <= k2));
+                        const uint32_t s = take1 ? i1 : i2;
+                        kr[i] = take1 ? k1 : k2;
                         if (HP) pr[i] = sm.sp[lpad(s)];
+                        i1 += take1 ? 1u : 0u;
+                        i2 += take1 ? 0u : 1u;
                     }
                 }
             }
@@ -1156,19 +1173,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
         // The node's merge: sk[0, nl) with sk[nl, nt), left first on equal keys.
         const uint32_t nrp = nt - nl;
         if (dx < nt) {
-            uint32_t l = dx > nrp ? dx - nrp : 0, h = min(dx, nl);
-            while (l < h) {
-                const uint32_t m = (l + h) >> 1;
-                if (sm.sk[lpad(m)] <= sm.sk[lpad(nl + dx - 1 - m)]) l = m + 1; else h = m;
-            }
+            const uint32_t l = lds_corank<kLog2QuadTile>(sm.sk, 0, nl, nl, nrp, dx);
             uint32_t ia = l, ib = nl + (dx - l);
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 if (dx + i < nt) {
-                    const bool take_a = (ib >= nt) || (ia < nl && sm.sk[lpad(ia)] <= sm.sk[lpad(ib)]);
-                    const uint32_t s = take_a ? ia++ : ib++;
-                    kr[i] = sm.sk[lpad(s)];
+                    const U ka = sm.sk[lpad(min(ia, nt - 1))], kb = sm.sk[lpad(min(ib, nt - 1))];
+                    const bool take_a = (ib >= nt) | ((ia < nl) & (ka <= kb));
+                    const uint32_t s = take_a ? ia : ib;
+                    kr[i] = take_a ? ka : kb;
                     if (HP) pr[i] = sm.sp[lpad(s)];
+                    ia += take_a ? 1u : 0u;
+                    ib += take_a ? 0u : 1u;
                 }
             }
         }
