@@ -196,9 +196,9 @@ ps_status ps_alphabetic_tree(const uint32_t *d_weights, uint64_t num_leaves, uin
  * still owns keys, payload and d_merge_cost.  opt->workspace must be NULL
  * (PS_ERR_INVALID_ARG otherwise).  A sort whose ps_workspace_bytes(n, 1,
  * key_type, payload != NULL, opt) exceeds 128 MiB returns PS_ERR_TOO_LARGE
- * with nothing enqueued; at the default minimum run that is above 6 513 408
- * 4-byte keys with a payload (10 647 503 without) or 4 702 720 8-byte keys
- * with a payload (6 523 343 without).  All calls on one device share that device's
+ * with nothing enqueued; at the default minimum run that is above 6 404 640
+ * 4-byte keys with a payload (10 359 840 without) or 4 645 728 8-byte keys
+ * with a payload (6 414 287 without).  All calls on one device share that device's
  * array, and each call rewrites what it needs: calls that overlap on one
  * device (on different streams or from different threads) race and give
  * undefined results, so the caller serialises them, e.g. on one stream.

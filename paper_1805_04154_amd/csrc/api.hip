@@ -165,6 +165,7 @@ struct Layout {
     size_t counters, starts, Q, P, leaf_depth, node_depth, aggF, aggB, inF, inB, mc, Lf, Rt, nsize;
     size_t unit_rec, unit_par, bigleaf, bigleaf_mode, biglist, bucket, node_rec, bucket_tile, leaf_tile, split, span;
     size_t child_l, child_r;
+    uint32_t unit_base[3] = {0, 0, 0};  // first record of each UnitKind's list
     size_t samp = 0;  // 4-byte keys that move: one order key per kSampleSpacing positions
     uint32_t rmax;
     uint64_t split_cap = 0;
@@ -223,8 +224,17 @@ static Layout make_layout(uint64_t N, uint64_t nseg, size_t kb, bool hp, uint32_
     L.Rt = take(at, r1 * 4);
     L.nsize = take(at, r1 * 4);
     if (moves) {
-        L.unit_rec = take(at, r1 * sizeof(UnitRec));
-        L.unit_par = take(at, r1);
+        // fused subtrees are disjoint: at most r1 of them in all, at most
+        // N / (kMaxMinRun + 1) single runs longer than any min-run, and at
+        // most r1 / kFuseRadixMinLeaves with that many leaves
+        const uint64_t cap_copy = std::min<uint64_t>(r1, N / (kMaxMinRun + 1) + 1);
+        const uint64_t cap_radix = r1 / kFuseRadixMinLeaves + 1;
+        L.unit_base[kUnitFew] = 0;
+        L.unit_base[kUnitCopy] = (uint32_t)r1;
+        L.unit_base[kUnitRadix] = (uint32_t)(r1 + cap_copy);
+        const size_t nrec = r1 + cap_copy + cap_radix;
+        L.unit_rec = take(at, nrec * sizeof(UnitRec));
+        L.unit_par = take(at, nrec);
         L.bigleaf = take(at, r1 * 4);
         L.bigleaf_mode = take(at, r1);
         L.biglist = take(at, r1 * 4);
@@ -598,6 +608,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     if (moves) {
         ta.lists.unit_rec = (UnitRec*)at(L.unit_rec);
         ta.lists.unit_par = (uint8_t*)at(L.unit_par);
+        for (int k = 0; k < 3; ++k) ta.lists.unit_base[k] = L.unit_base[k];
         ta.lists.bigleaf = (uint32_t*)at(L.bigleaf);
         ta.lists.bigleaf_mode = (uint8_t*)at(L.bigleaf_mode);
         ta.lists.biglist = (uint32_t*)at(L.biglist);
@@ -637,6 +648,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
         ma.cnt = cnt;
         ma.unit_rec = ta.lists.unit_rec;
         ma.unit_par = ta.lists.unit_par;
+        for (int k = 0; k < 3; ++k) ma.unit_base[k] = L.unit_base[k];
         ma.bigleaf = ta.lists.bigleaf;
         ma.bigleaf_mode = ta.lists.bigleaf_mode;
         ma.bucket = ta.lists.bucket;

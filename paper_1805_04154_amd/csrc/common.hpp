@@ -77,6 +77,16 @@ constexpr uint32_t kFuseRadixMinLeaves = 8;
 __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nleaves) {
     return (key_bytes == 4 || key_bytes == 8) && nleaves >= kFuseRadixMinLeaves;
 }
+// The kernel that forms a fused subtree of nleaves leaves and n elements: a
+// single natural run is copied (reversed if decreasing), a subtree of few
+// leaves is merged level by level, one of many leaves is radix-sorted.  The
+// subtrees of each kind form a list of their own.
+enum UnitKind : uint32_t { kUnitCopy = 0, kUnitFew = 1, kUnitRadix = 2 };
+__host__ __device__ constexpr uint32_t unit_kind(uint32_t key_bytes, uint32_t nleaves, uint32_t n) {
+    return (nleaves == 1 && n > (uint32_t)kMaxMinRun) ? kUnitCopy
+           : fuse_by_radix(key_bytes, nleaves)           ? kUnitRadix
+                                                         : kUnitFew;
+}
 
 // Global merge passes: merge-path tiles of 8192 outputs (1024 threads x 8)
 // by default for 4-byte keys, which halves the split searches; 8-byte keys

@@ -6,7 +6,7 @@ namespace ps {
 
 struct Counters {
     uint32_t r;            // number of leaves
-    uint32_t nunits;       // fused subtrees
+    uint32_t nunit[3];     // fused subtrees by the kernel that forms them (UnitKind)
     uint32_t nbigleaf;     // leaves longer than kFuse
     uint32_t nbig;         // nodes longer than kFuse
     uint32_t pcount[kMaxPass + 1];  // big nodes per pass key (power, or peeksort depth + 1)
@@ -59,8 +59,9 @@ struct UnitRec {
 };
 
 struct TreeLists {
-    UnitRec* unit_rec;
+    UnitRec* unit_rec;     // three lists, one per UnitKind, from unit_base[kind]
     uint8_t* unit_par;
+    uint32_t unit_base[3];
     uint32_t* bigleaf;
     uint8_t* bigleaf_mode;
     uint32_t* biglist;      // big nodes in discovery order; bit 31: the node absorbs a child
@@ -142,8 +143,9 @@ struct MoveArgs {
     const uint32_t* Rt;
     const uint8_t* node_depth;
     const Counters* cnt;
-    const UnitRec* unit_rec;
+    const UnitRec* unit_rec;   // three lists, one per UnitKind, from unit_base[kind]
     const uint8_t* unit_par;
+    uint32_t unit_base[3];
     const uint32_t* bigleaf;
     const uint8_t* bigleaf_mode;
     const uint32_t* bucket;

@@ -261,9 +261,10 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
     uint32_t* tp = sp + (HP ? kFuse : 0);
     uint16_t* hist = reinterpret_cast<uint16_t*>(tp + (HP ? kFuse : 0));
     uint16_t* rank = hist + kFuseWaves * 256;
-    const uint32_t nunits = a.cnt->nunits;
+    const uint32_t nunits = a.cnt->nunit[kUnitRadix];
     const uint32_t tid = threadIdx.x;
-    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+    for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
+        const uint32_t u = a.unit_base[kUnitRadix] + v;
         const UnitRec ur = a.unit_rec[u];
         const uint32_t nleaves = ur.ub - ur.ua;
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
@@ -316,10 +317,11 @@ template <int KT, bool HP>
 __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
     using K = Key<KT>;
     using raw = typename K::raw;
-    const uint32_t nunits = a.cnt->nunits;
+    const uint32_t nunits = a.cnt->nunit[kUnitCopy];
     const uint32_t tid = threadIdx.x;
     const raw* src = (const raw*)a.keys[0];
-    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+    for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
+        const uint32_t u = a.unit_base[kUnitCopy] + v;
         const UnitRec ur = a.unit_rec[u];
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         if (ur.ub - ur.ua != 1 || n <= (uint32_t)kMaxMinRun || n > (uint32_t)kFuse) continue;
@@ -380,11 +382,12 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) v
     __shared__ uint32_t sp[HP ? PADDED : 1];
     __shared__ uint32_t lst[KL + 1];
     __shared__ uint32_t snode[KN][3];  // per merge: first leaf, end leaf, power
-    const uint32_t nunits = a.cnt->nunits;
+    const uint32_t nunits = a.cnt->nunit[kUnitFew];
     const uint32_t tid = threadIdx.x;
     const raw* src = (const raw*)a.keys[0];
     auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
-    for (uint32_t u = blockIdx.x; u < nunits; u += gridDim.x) {
+    for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
+        const uint32_t u = a.unit_base[kUnitFew] + v;
         const UnitRec ur = a.unit_rec[u];
         const uint32_t ua = uni(ur.ua), nl = uni(ur.ub - ur.ua);
         const uint32_t lo = uni(ur.lo), n = uni(ur.hi - ur.lo);

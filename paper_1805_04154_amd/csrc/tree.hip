@@ -331,17 +331,19 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
     using K = Key<KT>;
     constexpr int kIt = 4;  // boundaries per thread per step
     __shared__ uint64_t sh64[kWaves];
-    __shared__ uint32_t base_sh[4];
+    __shared__ uint32_t base_sh[5];
     const uint32_t r = cnt->r;
     auto size_of = [&](uint32_t j) -> uint32_t { return nsize[j]; };
     // profiling element counts, summed per thread and added once per wave
     unsigned long long pr_leaf = 0, pr_fused = 0, pr_merge = 0;
     for (uint32_t i0 = blockIdx.x * kThreads * kIt; i0 < r; i0 += gridDim.x * kThreads * kIt) {
-        // flags of node i and leaf i for this thread's kIt indices; the four
-        // lists (big nodes, unit nodes, unit leaves, big leaves) take slots
-        // from one packed block scan and one atomic per list per step
+        // flags of node i and leaf i for this thread's kIt indices; the five
+        // lists (big nodes, the three kinds of units, big leaves) take slots
+        // from one packed block scan (12-bit fields) and one atomic per list
+        // per step
         uint8_t fl[kIt];
         uint8_t mode[kIt];
+        uint8_t kn[kIt], kl[kIt];  // kinds of the unit node and unit leaf
         uint32_t nlf[kIt], nrt[kIt];
         uint64_t mine = 0;
 #pragma unroll
@@ -350,6 +352,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             const bool valid = i < r;
             uint8_t f = 0;
             mode[it] = kLeafNoop;
+            kn[it] = kl[it] = 0;
             nlf[it] = nrt[it] = 0;
             // ---- node i (boundary between leaves i-1 and i)
             if (valid && i >= 1 && P[i] >= 1) {
@@ -380,6 +383,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                     }
                 } else if ((par == kNone) || size_of(par) > (uint32_t)kFuse) {
                     f |= 2;  // unit node
+                    kn[it] = (uint8_t)unit_kind(sizeof(typename K::ukey), nrt[it] - nlf[it], sz);
                 }
             }
             // ---- leaf i
@@ -394,32 +398,29 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
                     mode[it] = desc ? (moved ? kLeafRevCopy : kLeafRevInPlace) : (moved ? kLeafCopy : kLeafNoop);
                 } else if ((par == kNone) || size_of(par) > (uint32_t)kFuse) {
                     f |= 4;  // unit leaf
+                    kl[it] = (uint8_t)unit_kind(sizeof(typename K::ukey), 1, len);
                 }
             }
             fl[it] = f;
-            mine += (uint64_t)(f & 1) + ((uint64_t)((f >> 1) & 1) << 16) + ((uint64_t)((f >> 2) & 1) << 32) +
-                    ((uint64_t)((f >> 3) & 1) << 48);
+            // fields: big nodes, units of kind 0, 1, 2, big leaves (each
+            // count <= kThreads * kIt < 2^12)
+            mine += (uint64_t)(f & 1) + ((uint64_t)((f >> 3) & 1) << 48);
+            if (f & 2) mine += 1ull << (12 * (1 + kn[it]));
+            if (f & 4) mine += 1ull << (12 * (1 + kl[it]));
         }
+        static_assert(kThreads * kIt < (1 << 12), "block counts fit 12-bit fields");
         uint64_t total;
         uint64_t off = block_excl_sum64(mine, sh64, &total);
-        if (threadIdx.x < 4) {
-            const uint32_t c = (uint32_t)(total >> (16 * threadIdx.x)) & 0xFFFFu;
-            uint32_t* ctr = threadIdx.x == 0 ? &cnt->nbig : threadIdx.x == 1 ? &cnt->nunits
-                          : threadIdx.x == 2 ? &cnt->nunits : &cnt->nbigleaf;
-            // unit nodes and unit leaves share one list: reserve both from
-            // thread 1, in that order
-            if (threadIdx.x == 1) {
-                const uint32_t cl = (uint32_t)(total >> 32) & 0xFFFFu;
-                base_sh[1] = (c + cl) ? atomicAdd(ctr, c + cl) : 0u;
-                base_sh[2] = base_sh[1] + c;
-            } else if (threadIdx.x != 2) {
-                base_sh[threadIdx.x] = c ? atomicAdd(ctr, c) : 0u;
-            }
+        if (threadIdx.x < 5) {
+            const uint32_t c = (uint32_t)(total >> (12 * threadIdx.x)) & 0xFFFu;
+            uint32_t* ctr = threadIdx.x == 0 ? &cnt->nbig : threadIdx.x == 4 ? &cnt->nbigleaf
+                                                         : &cnt->nunit[threadIdx.x - 1];
+            base_sh[threadIdx.x] = c ? atomicAdd(ctr, c) : 0u;
         }
         __syncthreads();
-        uint32_t pos[4];
+        uint32_t pos[5];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pos[q] = base_sh[q] + ((uint32_t)(off >> (16 * q)) & 0xFFFFu);
+        for (int q = 0; q < 5; ++q) pos[q] = base_sh[q] + ((uint32_t)(off >> (12 * q)) & 0xFFFu);
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
@@ -427,19 +428,19 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const typename Key<K
             const uint8_t f = fl[it];
             if (f & 1) L.biglist[pos[0]++] = i | ((f & 16) ? 0x80000000u : 0u);
             if (f & 2) {
-                const uint32_t slot = pos[1]++;
+                const uint32_t slot = L.unit_base[kn[it]] + pos[1 + kn[it]]++;
                 pr_fused += starts[nrt[it]] - starts[nlf[it]];
                 L.unit_rec[slot] = UnitRec{nlf[it], nrt[it], starts[nlf[it]], starts[nrt[it]]};
                 L.unit_par[slot] = node_buf(pass_level(node_depth[i], L.levels), L.nbuf);
             }
             if (f & 4) {
-                const uint32_t slot = pos[2]++;
+                const uint32_t slot = L.unit_base[kl[it]] + pos[1 + kl[it]]++;
                 pr_fused += starts[i + 1] - starts[i];
                 L.unit_rec[slot] = UnitRec{i, i + 1, starts[i], starts[i + 1]};
                 L.unit_par[slot] = node_buf(pass_level(leaf_depth[i], L.levels), L.nbuf);
             }
             if (f & 8) {
-                const uint32_t slot = pos[3]++;
+                const uint32_t slot = pos[4]++;
                 if (mode[it] != kLeafNoop) pr_leaf += starts[i + 1] - starts[i];
                 L.bigleaf[slot] = i;
                 L.bigleaf_mode[slot] = mode[it];
