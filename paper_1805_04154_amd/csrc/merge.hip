@@ -545,6 +545,238 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) v
     }
 }
 
+// Direct load of one dword per lane from global memory into LDS (gfx950
+// global_load_lds): lane l of the wave writes its dword to lds[l], so lds
+// must be the same for the whole wave.  No VGPR holds the data, and the
+// load stays in flight while the wave goes on (the next barrier after an
+// s_waitcnt vmcnt(0) publishes it).
+__device__ __forceinline__ void lds_dma_dword(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// A block barrier for LDS work only: this wave's LDS reads and writes are
+// done, then all waves meet.  Unlike __syncthreads it is no release fence,
+// so it does not wait for direct loads into LDS still in flight; compiler
+// fences keep memory accesses on their side of it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt at their maxima (no wait)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+constexpr int kStageMeta = 64;  // per staged subtree: starts, then Lf, Rt and P of the merges
+// Staging of one fused subtree of kUnitFew (4-byte keys), all by direct
+// loads that every wave issues for its own part:
+//   - with data: its keys and payload, unpadded, and the tree data of its
+//     leaves and merges (raw global values) in meta;
+//   - the dword of unit_par that holds its destination byte (nxt[64]), and,
+//     when there is one, the record of the subtree this block takes after
+//     it (nxt[0..3]), so that no load waits at the top of the next round.
+template <bool HP>
+__device__ __forceinline__ void fused_stage(const MoveArgs& a, const UnitRec ur, bool data, uint32_t u,
+                                            bool has_next, uint32_t u_next, uint32_t* stk, uint32_t* stp,
+                                            uint32_t* meta, uint32_t* nxt) {
+    constexpr int NT = kFusedNT, IT = kFuse / kFusedNT;
+    const uint32_t lo = ur.lo, n = ur.hi - ur.lo, ua = ur.ua, nl = ur.ub - ur.ua;
+    const uint32_t tid = threadIdx.x, w0 = tid & ~63u, lane = tid & 63u;
+    if (data) {
+        const uint32_t* ks = (const uint32_t*)a.keys[0] + lo;
+        const uint32_t* ps = a.pay[0] + lo;
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            if (i * NT + w0 < n) {  // whole waves past the end load nothing
+                const uint32_t x = min(i * NT + tid, n - 1);
+                lds_dma_dword(ks + x, stk + i * NT + w0);
+                if (HP) lds_dma_dword(ps + x, stp + i * NT + w0);
+            }
+        }
+        if (w0 == 0) {
+            lds_dma_dword(a.starts + ua + min(lane, nl), meta);
+            if (nl > 1) {
+                const uint32_t j = ua + 1 + min(lane, nl - 2);
+                lds_dma_dword(a.Lf + j, meta + kStageMeta);
+                lds_dma_dword(a.Rt + j, meta + 2 * kStageMeta);
+                // the aligned dword that holds byte j of P (P sits in a
+                // 256-byte aligned allocation that is not the workspace's last)
+                lds_dma_dword(a.P + (j & ~3u), meta + 3 * kStageMeta);
+            }
+        }
+    }
+    if (w0 == 64) {
+        // unit_par and unit_rec sit in 256-byte aligned allocations (not the
+        // workspace's last), unit records are 16 bytes
+        lds_dma_dword(a.unit_par + (u & ~3u), nxt + 64);
+        if (has_next) lds_dma_dword((const uint32_t*)(a.unit_rec + u_next) + min(lane, 3u), nxt);
+    }
+}
+
+// fused_kernel for 4-byte keys with the next subtree's data loaded while the
+// current one is merged: direct loads fill an unpadded staging copy in LDS,
+// leaf formation reads it and writes the padded working copy, and the loads
+// of the next subtree are issued right after.  The leaves and merges are the
+// same as fused_kernel's.  LDS: about 68 KiB with a payload, two blocks per CU.
+template <int KT, bool HP>
+__global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) void fused_staged_kernel(MoveArgs a) {
+    constexpr int NT = kFusedNT, IT = kFuse / kFusedNT;
+    using K = Key<KT>;
+    using U = typename K::ukey;
+    using raw = typename K::raw;
+    static_assert(sizeof(raw) == 4 && IT == 4, "staging holds 4-byte keys, one 16-byte vector per thread");
+    constexpr uint32_t KL = kFuseRadixMinLeaves;
+    constexpr uint32_t KN = KL - 2;
+    constexpr uint32_t PADDED = kFuse + kFuse / 8;
+    __shared__ U sk[PADDED];
+    __shared__ uint32_t sp[HP ? PADDED : 1];
+    __shared__ __align__(16) uint32_t stk[kFuse];
+    __shared__ __align__(16) uint32_t stp[HP ? kFuse : 4];
+    __shared__ uint32_t meta[4 * kStageMeta];
+    __shared__ uint32_t nxt[128];
+    __shared__ uint32_t lst[KL + 1];
+    __shared__ uint32_t snode[KN][3];  // per merge: first leaf, end leaf, power
+    const uint32_t nunits = a.cnt->nunit[kUnitFew], base = a.unit_base[kUnitFew];
+    const uint32_t tid = threadIdx.x, G = gridDim.x;
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
+    // Units of this list hold 1 to kFuseRadixMinLeaves - 1 leaves and at most
+    // kFuse elements (classify_kernel); one that does not is skipped whole.
+    auto valid = [](const UnitRec& r) {
+        const uint32_t nl = r.ub - r.ua, n = r.hi - r.lo;
+        return nl >= 1 && nl < KL && n >= 1 && n <= (uint32_t)kFuse;
+    };
+    uint32_t v = blockIdx.x;
+    UnitRec ur{0, 0, 0, 0};
+    if (v < nunits) {
+        const UnitRec r = a.unit_rec[base + v];
+        ur = UnitRec{uni(r.ua), uni(r.ub), uni(r.lo), uni(r.hi)};
+        fused_stage<HP>(a, ur, valid(ur), base + v, v + G < nunits, base + v + G, stk, stp, meta, nxt);
+    }
+    for (; v < nunits; v += G) {
+        const uint32_t vn = v + G;
+        const bool ok = valid(ur);
+        const uint32_t ua = ur.ua, nl = ur.ub - ur.ua, lo = ur.lo, n = ur.hi - ur.lo;
+        const uint32_t nn = nl - 1;
+        wait_vmem();
+        __syncthreads();  // staged data in LDS; the previous subtree's last reads are done
+        const uint32_t par = (uni(nxt[64]) >> (8 * ((base + v) & 3))) & 0xFFu;
+        const UnitRec nr = vn < nunits ? UnitRec{uni(nxt[0]), uni(nxt[1]), uni(nxt[2]), uni(nxt[3])}
+                                       : UnitRec{0, 0, 0, 0};
+        unsigned long long pm = 0;
+        const uint32_t x0 = tid * IT;
+        U kr[IT];
+        uint32_t pr[IT];
+        uint16_t np[IT];
+        if (ok) {
+            // Leaf formation (R1): staging -> padded working copy, each leaf
+            // stably sorted on the way.
+            const uint4 kv = *reinterpret_cast<const uint4*>(stk + x0);
+            uint4 pv = make_uint4(0, 0, 0, 0);
+            if (HP) pv = *reinterpret_cast<const uint4*>(stp + x0);
+            const uint32_t kw[IT] = {kv.x, kv.y, kv.z, kv.w};
+            const uint32_t pw[IT] = {pv.x, pv.y, pv.z, pv.w};
+            auto st = [&](uint32_t l) { return meta[l] - lo; };
+            auto okey = [&](uint32_t y) { return K::ord(__builtin_bit_cast(raw, stk[y])); };
+            uint32_t l = 0;
+            while (l + 1 < nl && st(l + 1) <= x0) ++l;
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = x0 + i;
+                if (x < n) {
+                    while (st(l + 1) <= x) ++l;
+                    const uint32_t ls = st(l), le = st(l + 1);
+                    const U key = K::ord(__builtin_bit_cast(raw, kw[i]));
+                    uint32_t dpos;
+                    if (le - ls <= (uint32_t)kMaxMinRun) {
+                        uint32_t rank = 0;
+#pragma unroll 1
+                        for (uint32_t y = ls; y < le; ++y) {
+                            const U o = okey(y);
+                            rank += (o < key) || (o == key && y < x);
+                        }
+                        dpos = ls + rank;
+                    } else {
+                        const bool desc = okey(ls + 1) < okey(ls);
+                        dpos = desc ? (ls + le - 1 - x) : x;
+                    }
+                    sk[lpad(dpos)] = key;
+                    if (HP) sp[lpad(dpos)] = pw[i];
+                }
+            }
+            if (tid <= nl) lst[tid] = meta[tid] - lo;
+            if (tid < nn) {
+                snode[tid][0] = meta[kStageMeta + tid] - ua;
+                snode[tid][1] = meta[2 * kStageMeta + tid] - ua;
+                snode[tid][2] = (meta[3 * kStageMeta + tid] >> (8 * ((ua + 1 + tid) & 3))) & 0xFFu;
+            }
+        }
+        __syncthreads();  // staging is free: stage the next subtree
+        if (vn < nunits)
+            fused_stage<HP>(a, nr, valid(nr), base + vn, vn + G < nunits, base + vn + G, stk, stp, meta, nxt);
+        if (ok) {
+            for (uint32_t m = 0; m < nn; ++m) pm |= 1ull << uni(snode[m][2]);
+            raw* dst = (raw*)pick3u(a.keys, par);
+            uint32_t* pdst = pick3u(a.pay, par);
+            // Merges, deepest power first.
+            while (pm) {
+                const uint32_t p = 63 - __clzll(pm);
+                pm &= ~(1ull << p);
+#pragma unroll
+                for (int i = 0; i < IT; ++i) np[i] = (uint16_t)(x0 + i);  // copied unless merged
+#pragma unroll 1
+                for (uint32_t m = 0; m < nn; ++m) {
+                    if (uni(snode[m][2]) != p) continue;
+                    const uint32_t nlo = uni(lst[snode[m][0]]), nmid = uni(lst[m + 1]), nhi = uni(lst[snode[m][1]]);
+                    if (nlo < x0 + IT && x0 < nhi) {
+                        const uint32_t s0 = max(x0, nlo);
+                        const uint32_t d = s0 - nlo, la = nmid - nlo, lb = nhi - nmid;
+                        uint32_t lw = d > lb ? d - lb : 0, h = min(d, la);
+                        while (lw < h) {
+                            const uint32_t mm = (lw + h) >> 1;
+                            if (sk[lpad(nlo + mm)] <= sk[lpad(nmid + d - 1 - mm)]) lw = mm + 1; else h = mm;
+                        }
+                        uint32_t ia = nlo + lw, ib = nmid + (d - lw);
+#pragma unroll
+                        for (int i = 0; i < IT; ++i) {
+                            const uint32_t x = x0 + i;
+                            if (x >= s0 && x < nhi) {
+                                const bool take_a = (ib >= nhi) || (ia < nmid && sk[lpad(ia)] <= sk[lpad(ib)]);
+                                np[i] = (uint16_t)(take_a ? ia++ : ib++);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    if (x0 + i < n) {
+                        kr[i] = sk[lpad(np[i])];
+                        if (HP) pr[i] = sp[lpad(np[i])];
+                    }
+                }
+                lds_barrier();
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    if (x0 + i < n) {
+                        sk[lpad(x0 + i)] = kr[i];
+                        if (HP) sp[lpad(x0 + i)] = pr[i];
+                    }
+                }
+                lds_barrier();
+            }
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t x = tid + i * NT;
+                if (x < n) {
+                    const U key = sk[lpad(x)];
+                    dst[lo + x] = K::unord(key);
+                    if (HP) pdst[lo + x] = sp[lpad(x)];
+                    put_sample(a.samp, lo + x, key);
+                }
+            }
+        }
+        ur = nr;
+    }
+}
+
 // ------------------------------------------------------------ merge passes
 
 template <int KT, int TILE>
@@ -1345,7 +1577,12 @@ template <int KT, bool HP>
 static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t grid, hipStream_t st, hipEvent_t ev0,
                            hipEvent_t ev1) {
     if (stage == 0) launch(big_leaf_kernel<KT, HP>, grid, kThreads, 0, st, ev0, ev1, a);
-    else if (stage == 1) launch(fused_kernel<KT, HP>, grid, kFusedNT, 0, st, ev0, ev1, a);
+    else if (stage == 1) {
+        if constexpr (sizeof(typename Key<KT>::raw) == 4)
+            launch(fused_staged_kernel<KT, HP>, grid, kFusedNT, 0, st, ev0, ev1, a);
+        else
+            launch(fused_kernel<KT, HP>, grid, kFusedNT, 0, st, ev0, ev1, a);
+    }
     else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
