@@ -608,7 +608,13 @@ __device__ __forceinline__ void fused_stage(const MoveArgs& a, const UnitRec ur,
         // unit_par and unit_rec sit in 256-byte aligned allocations (not the
         // workspace's last), unit records are 16 bytes
         lds_dma_dword(a.unit_par + (u & ~3u), nxt + 64);
-        if (has_next) lds_dma_dword((const uint32_t*)(a.unit_rec + u_next) + min(lane, 3u), nxt);
+        if (has_next) {
+            // (opaque to the compiler, so that no loop-invariant part of the
+            // per-lane address is kept in VGPRs across the merges)
+            const uint32_t* rp = (const uint32_t*)(a.unit_rec + u_next);
+            asm volatile("" : "+s"(rp));
+            lds_dma_dword(rp + min(lane, 3u), nxt);
+        }
     }
 }
 
@@ -633,8 +639,7 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) v
     __shared__ __align__(16) uint32_t stp[HP ? kFuse : 4];
     __shared__ uint32_t meta[4 * kStageMeta];
     __shared__ uint32_t nxt[128];
-    __shared__ uint32_t lst[KL + 1];
-    __shared__ uint32_t snode[KN][3];  // per merge: first leaf, end leaf, power
+    __shared__ uint4 mrg[KN];  // per merge: nlo, nmid, nhi (subtree positions), power
     const uint32_t nunits = a.cnt->nunit[kUnitFew], base = a.unit_base[kUnitFew];
     const uint32_t tid = threadIdx.x, G = gridDim.x;
     auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); };
@@ -670,77 +675,132 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) v
             // Leaf formation (R1): staging -> padded working copy, each leaf
             // stably sorted on the way.
             const uint4 kv = *reinterpret_cast<const uint4*>(stk + x0);
-            uint4 pv = make_uint4(0, 0, 0, 0);
-            if (HP) pv = *reinterpret_cast<const uint4*>(stp + x0);
             const uint32_t kw[IT] = {kv.x, kv.y, kv.z, kv.w};
-            const uint32_t pw[IT] = {pv.x, pv.y, pv.z, pv.w};
             auto st = [&](uint32_t l) { return meta[l] - lo; };
             auto okey = [&](uint32_t y) { return K::ord(__builtin_bit_cast(raw, stk[y])); };
+            // A leaf longer than kMaxMinRun is a natural run: kept, or
+            // reversed if strictly descending.  A shorter one is sorted by
+            // ranks: each of this thread's elements in such leaves counts the
+            // leaf's elements ordered before it, in one pass over the union
+            // of those leaves (four independent LDS reads a step).
+            U key[IT];
+            uint32_t dpos[IT], sb[IT];  // sb: short leaf bounds, ls | le << 16 (none: 0)
+            uint32_t ys = kFuse, ye = 0;
             uint32_t l = 0;
             while (l + 1 < nl && st(l + 1) <= x0) ++l;
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 const uint32_t x = x0 + i;
+                key[i] = K::ord(__builtin_bit_cast(raw, kw[i]));
+                dpos[i] = x;
+                sb[i] = 0;
                 if (x < n) {
                     while (st(l + 1) <= x) ++l;
                     const uint32_t ls = st(l), le = st(l + 1);
-                    const U key = K::ord(__builtin_bit_cast(raw, kw[i]));
-                    uint32_t dpos;
                     if (le - ls <= (uint32_t)kMaxMinRun) {
-                        uint32_t rank = 0;
-#pragma unroll 1
-                        for (uint32_t y = ls; y < le; ++y) {
-                            const U o = okey(y);
-                            rank += (o < key) || (o == key && y < x);
-                        }
-                        dpos = ls + rank;
+                        sb[i] = ls | (le << 16);
+                        dpos[i] = ls;
+                        ys = min(ys, ls);
+                        ye = max(ye, le);
                     } else {
                         const bool desc = okey(ls + 1) < okey(ls);
-                        dpos = desc ? (ls + le - 1 - x) : x;
+                        dpos[i] = desc ? (ls + le - 1 - x) : x;
                     }
-                    sk[lpad(dpos)] = key;
-                    if (HP) sp[lpad(dpos)] = pw[i];
                 }
             }
-            if (tid <= nl) lst[tid] = meta[tid] - lo;
+#pragma unroll 1
+            for (uint32_t y = ys; y < ye; y += 4) {
+                U o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k] = okey(min(y + k, (uint32_t)kFuse - 1));
+#pragma unroll
+                for (int i = 0; i < IT; ++i) {
+                    const uint32_t ls = sb[i] & 0xFFFFu, le = sb[i] >> 16;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t yk = y + k;
+                        if (yk >= ls && yk < le)
+                            dpos[i] += (o[k] < key[i]) || (o[k] == key[i] && yk < x0 + i);
+                    }
+                }
+            }
+            uint4 pv = make_uint4(0, 0, 0, 0);
+            if (HP) pv = *reinterpret_cast<const uint4*>(stp + x0);
+            const uint32_t pw[IT] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                if (x0 + i < n) {
+                    sk[lpad(dpos[i])] = key[i];
+                    if (HP) sp[lpad(dpos[i])] = pw[i];
+                }
+            }
+            // Each merge's range [nlo, nmid) + [nmid, nhi) and power, once.
             if (tid < nn) {
-                snode[tid][0] = meta[kStageMeta + tid] - ua;
-                snode[tid][1] = meta[2 * kStageMeta + tid] - ua;
-                snode[tid][2] = (meta[3 * kStageMeta + tid] >> (8 * ((ua + 1 + tid) & 3))) & 0xFFu;
+                const uint32_t f = meta[kStageMeta + tid] - ua, e = meta[2 * kStageMeta + tid] - ua;
+                mrg[tid] = make_uint4(meta[f] - lo, meta[tid + 1] - lo, meta[e] - lo,
+                                      (meta[3 * kStageMeta + tid] >> (8 * ((ua + 1 + tid) & 3))) & 0xFFu);
             }
         }
         __syncthreads();  // staging is free: stage the next subtree
         if (vn < nunits)
             fused_stage<HP>(a, nr, valid(nr), base + vn, vn + G < nunits, base + vn + G, stk, stp, meta, nxt);
         if (ok) {
-            for (uint32_t m = 0; m < nn; ++m) pm |= 1ull << uni(snode[m][2]);
+            // powers of the merges, block-uniform (kNone past the last)
+            uint32_t mp[KN];
+#pragma unroll
+            for (uint32_t m = 0; m < KN; ++m) {
+                mp[m] = m < nn ? uni(mrg[m].w) : 64u;
+                if (m < nn) pm |= 1ull << mp[m];
+            }
             raw* dst = (raw*)pick3u(a.keys, par);
             uint32_t* pdst = pick3u(a.pay, par);
             // Merges, deepest power first.
             while (pm) {
                 const uint32_t p = 63 - __clzll(pm);
                 pm &= ~(1ull << p);
+                uint32_t todo = 0;
+#pragma unroll
+                for (uint32_t m = 0; m < KN; ++m) todo |= (mp[m] == p ? 1u : 0u) << m;
 #pragma unroll
                 for (int i = 0; i < IT; ++i) np[i] = (uint16_t)(x0 + i);  // copied unless merged
 #pragma unroll 1
-                for (uint32_t m = 0; m < nn; ++m) {
-                    if (uni(snode[m][2]) != p) continue;
-                    const uint32_t nlo = uni(lst[snode[m][0]]), nmid = uni(lst[m + 1]), nhi = uni(lst[snode[m][1]]);
+                while (todo) {
+                    const uint32_t m = __builtin_ctz(todo);
+                    todo &= todo - 1;
+                    const uint4 r = mrg[m];
+                    const uint32_t nlo = uni(r.x), nmid = uni(r.y), nhi = uni(r.z);
                     if (nlo < x0 + IT && x0 < nhi) {
                         const uint32_t s0 = max(x0, nlo);
                         const uint32_t d = s0 - nlo, la = nmid - nlo, lb = nhi - nmid;
-                        uint32_t lw = d > lb ? d - lb : 0, h = min(d, la);
-                        while (lw < h) {
-                            const uint32_t mm = (lw + h) >> 1;
-                            if (sk[lpad(nlo + mm)] <= sk[lpad(nmid + d - 1 - mm)]) lw = mm + 1; else h = mm;
+                        // merge-path co-rank of diagonal d (ties to the left
+                        // run): the largest c in [lo_c, hi_c] whose element
+                        // a[c - 1] is not above b[d - c], by a fixed number of
+                        // halving steps (the same for the whole block)
+                        uint32_t c = d > lb ? d - lb : 0;
+                        const uint32_t hi_c = min(d, la);
+                        const int steps = 32 - __clz((int)min(la, lb));
+#pragma unroll 1
+                        for (int k = steps - 1; k >= 0; --k) {
+                            const uint32_t q = c + (1u << k), qc = min(q, hi_c);
+                            if (q <= hi_c && sk[lpad(nlo + qc - 1)] <= sk[lpad(nmid + d - qc)]) c = q;
                         }
-                        uint32_t ia = nlo + lw, ib = nmid + (d - lw);
+                        // merge steps: the two run heads in registers, one
+                        // LDS read per step
+                        uint32_t ia = nlo + c, ib = nmid + (d - c);
+                        U ka = sk[lpad(ia)], kb = sk[lpad(min(ib, (uint32_t)kFuse - 1))];
 #pragma unroll
                         for (int i = 0; i < IT; ++i) {
                             const uint32_t x = x0 + i;
                             if (x >= s0 && x < nhi) {
-                                const bool take_a = (ib >= nhi) || (ia < nmid && sk[lpad(ia)] <= sk[lpad(ib)]);
-                                np[i] = (uint16_t)(take_a ? ia++ : ib++);
+                                const bool ta = (ib >= nhi) || (ia < nmid && ka <= kb);
+                                np[i] = (uint16_t)(ta ? ia : ib);
+                                ia += ta ? 1u : 0u;
+                                ib += ta ? 0u : 1u;
+                                if (i + 1 < IT) {
+                                    const U v = sk[lpad(min(ta ? ia : ib, (uint32_t)kFuse - 1))];
+                                    ka = ta ? v : ka;
+                                    kb = ta ? kb : v;
+                                }
                             }
                         }
                     }
