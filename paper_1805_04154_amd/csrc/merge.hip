@@ -608,12 +608,13 @@ __device__ __forceinline__ void fused_stage(const MoveArgs& a, const UnitRec ur,
         // unit_par and unit_rec sit in 256-byte aligned allocations (not the
         // workspace's last), unit records are 16 bytes
         lds_dma_dword(a.unit_par + (u & ~3u), nxt + 64);
-        if (has_next) {
-            // (opaque to the compiler, so that no loop-invariant part of the
-            // per-lane address is kept in VGPRs across the merges)
-            const uint32_t* rp = (const uint32_t*)(a.unit_rec + u_next);
+        if (has_next && lane == 0) {
+            // one 16-byte record by one lane (opaque to the compiler, so that
+            // no loop-invariant part of its address stays in VGPRs)
+            const UnitRec* rp = a.unit_rec + u_next;
             asm volatile("" : "+s"(rp));
-            lds_dma_dword(rp + min(lane, 3u), nxt);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)rp,
+                                             (__attribute__((address_space(3))) void*)nxt, 16, 0, 0);
         }
     }
 }
@@ -781,7 +782,9 @@ __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) v
                         const int steps = 32 - __clz((int)min(la, lb));
 #pragma unroll 1
                         for (int k = steps - 1; k >= 0; --k) {
-                            const uint32_t q = c + (1u << k), qc = min(q, hi_c);
+                            // (qc >= 1 keeps both reads inside the two runs
+                            // when hi_c is 0; the step is then not taken)
+                            const uint32_t q = c + (1u << k), qc = max(1u, min(q, hi_c));
                             if (q <= hi_c && sk[lpad(nlo + qc - 1)] <= sk[lpad(nmid + d - qc)]) c = q;
                         }
                         // merge steps: the two run heads in registers, one
