@@ -32,7 +32,7 @@ def candidates(small: bool = False) -> list[dict]:
     levels = (1, 2)
     tiles = (8192, 4096, 2048)
     merge_grids = (1024, 2048, 4096) if not small else (2048,)
-    fused_grids = (1024, 2048) if not small else (2048,)
+    fused_grids = (2048, 4096, 8192) if not small else (2048,)
     split_grids = (1024, 2048, 4096) if not small else (2048,)
     out = []
     for lv, t, gm, gf, gs in itertools.product(levels, tiles, merge_grids, fused_grids, split_grids):

@@ -152,11 +152,11 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
 // eight ballots, and a per-wave counter per digit carries the count from one
 // slot to the next, so ranks follow the current order (stability).  The
 // per-wave counts then become destinations by a scan over (digit, wave).
-// hist: kFuseWaves x 256 counters, rank: kFuse entries.  Returns true if the
+// hist: kFuseWaves x 256 counters; ranks stay in registers.  Returns true if the
 // result ended in tk/tp.  Block-uniform; all threads call.
 template <class U, bool HP>
 __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uint32_t* tp, uint32_t n,
-                                                 uint16_t* hist, uint16_t* rank, uint32_t* sh,
+                                                 uint16_t* hist, uint32_t* sh,
                                                  unsigned long long* red) {
     constexpr int BITS = 8 * sizeof(U);
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -181,8 +181,12 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
     for (int s = 0; s < BITS; s += 8) {
         if (((diff >> s) & (U)0xFF) == 0) continue;  // every key has the same digit
         for (uint32_t i = lane; i < 256; i += 64) hw[i] = 0;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll 1
+        // Each slot's digit, its rank among the slot's lanes with that digit
+        // and their count (independent across slots), then the per-wave
+        // counters in slot order; ranks stay in registers for the scatter.
+        uint32_t dg[kFuseItems], rk[kFuseItems];
+        uint32_t pc[kFuseItems];
+#pragma unroll
         for (int q = 0; q < kFuseItems; ++q) {
             const uint32_t x = w * 512 + q * 64 + lane;
             const bool valid = x < n;
@@ -193,12 +197,18 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
                 const uint64_t bb = __ballot((d >> b) & 1u);
                 peers &= ((d >> b) & 1u) ? bb : ~bb;
             }
-            const uint32_t before = (uint32_t)__popcll(peers & lt);
-            const uint32_t base = valid ? hw[d] : 0u;
+            dg[q] = d;
+            rk[q] = (uint32_t)__popcll(peers & lt);
+            pc[q] = valid ? (uint32_t)__popcll(peers) : 0u;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < kFuseItems; ++q) {
+            const uint32_t base = hw[dg[q]];
             __builtin_amdgcn_wave_barrier();
-            if (valid && before == 0) hw[d] = (uint16_t)(base + (uint32_t)__popcll(peers));
+            if (pc[q] != 0 && rk[q] == 0) hw[dg[q]] = (uint16_t)(base + pc[q]);
             __builtin_amdgcn_wave_barrier();
-            if (valid) rank[x] = (uint16_t)(base + before);
+            rk[q] += base;
         }
         __syncthreads();
         // hist[w][d] := elements before (digit d, wave w) in the pass's order
@@ -219,9 +229,8 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
         for (int q = 0; q < kFuseItems; ++q) {
             const uint32_t x = w * 512 + q * 64 + lane;
             if (x < n) {
-                const U key = sk[x];
-                const uint32_t dst = hw[(uint32_t)((key >> s) & (U)0xFF)] + rank[x];
-                tk[dst] = key;
+                const uint32_t dst = hw[dg[q]] + rk[q];
+                tk[dst] = sk[x];
                 if (HP) tp[dst] = sp[x];
             }
         }
@@ -238,9 +247,9 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
 }
 
 // LDS of fused_radix_kernel: keys and payloads twice, the per-wave digit
-// counters, the ranks, and a 128-byte header (wave totals, a reduction word).
+// counters, and a 128-byte header (wave totals, a reduction word).
 __host__ __device__ constexpr uint32_t radix_lds_bytes(uint32_t key_bytes, bool hp) {
-    return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2 + kFuse * 2;
+    return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2;
 }
 
 // Fused subtrees with many leaves: every merge in a subtree is
@@ -260,7 +269,6 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
     uint32_t* sp = reinterpret_cast<uint32_t*>(tk + kFuse);
     uint32_t* tp = sp + (HP ? kFuse : 0);
     uint16_t* hist = reinterpret_cast<uint16_t*>(tp + (HP ? kFuse : 0));
-    uint16_t* rank = hist + kFuseWaves * 256;
     const uint32_t nunits = a.cnt->nunit[kUnitRadix];
     const uint32_t tid = threadIdx.x;
     for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
             }
         }
         __syncthreads();
-        const bool alt = block_radix_sort<U, HP>(sk, sp, tk, tp, n, hist, rank, sh, red);
+        const bool alt = block_radix_sort<U, HP>(sk, sp, tk, tp, n, hist, sh, red);
         const U* ok = alt ? tk : sk;
         const uint32_t* op = alt ? tp : sp;
 #pragma unroll
@@ -312,38 +320,49 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
 // A fused unit that is a single natural run (longer than any min-run
 // extension): copied to its array, reversed if strictly decreasing, without
 // LDS.  Every element is loaded before any is stored, since a run that is a
-// whole segment is written in place.
+// whole segment is written in place.  Small blocks (256 threads x 16
+// elements) keep more units in flight per CU; whether the run decreases comes
+// from its first two elements as loaded (a flag per parity of the round, so
+// that one barrier a unit suffices).
+constexpr int kCopyThreads = 256;
+constexpr int kCopyItems = kFuse / kCopyThreads;
 template <int KT, bool HP>
-__global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
+__global__ __launch_bounds__(kCopyThreads) __attribute__((amdgpu_waves_per_eu(sizeof(typename Key<KT>::raw) == 4 ? 8 : 4))) void unit_copy_kernel(MoveArgs a) {
     using K = Key<KT>;
     using raw = typename K::raw;
+    __shared__ uint32_t desc_sh[2];
     const uint32_t nunits = a.cnt->nunit[kUnitCopy];
     const uint32_t tid = threadIdx.x;
     const raw* src = (const raw*)a.keys[0];
-    for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
+    uint32_t round = 0;
+    for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x, ++round) {
         const uint32_t u = a.unit_base[kUnitCopy] + v;
         const UnitRec ur = a.unit_rec[u];
         const uint32_t lo = ur.lo, n = ur.hi - ur.lo;
         if (ur.ub - ur.ua != 1 || n <= (uint32_t)kMaxMinRun || n > (uint32_t)kFuse) continue;
         raw* dst = (raw*)pick3u(a.keys, a.unit_par[u]);
         uint32_t* pdst = pick3u(a.pay, a.unit_par[u]);
-        const bool desc = K::ord(src[lo + 1]) < K::ord(src[lo]);
         const bool in_place = (const void*)dst == (const void*)src;
-        raw kv[kFuseItems];
-        uint32_t pv[kFuseItems];
+        raw kv[kCopyItems];
+        uint32_t pv[kCopyItems];
 #pragma unroll
-        for (int i = 0; i < kFuseItems; ++i) {
-            const uint32_t x = tid + i * kFuseThreads;
+        for (int i = 0; i < kCopyItems; ++i) {
+            const uint32_t x = tid + i * kCopyThreads;
             if (x < n) {
                 kv[i] = src[lo + x];
                 if (HP) pv[i] = a.pay[0][lo + x];
             }
         }
+        if (tid < 64) {
+            const raw k1 = __shfl(kv[0], 1);  // n > kMaxMinRun: elements 0 and 1 exist
+            if (tid == 0) desc_sh[round & 1] = K::ord(k1) < K::ord(kv[0]) ? 1u : 0u;
+        }
         __syncthreads();
+        const bool desc = desc_sh[round & 1] != 0;
         if (desc || !in_place) {
 #pragma unroll
-            for (int i = 0; i < kFuseItems; ++i) {
-                const uint32_t x = tid + i * kFuseThreads;
+            for (int i = 0; i < kCopyItems; ++i) {
+                const uint32_t x = tid + i * kCopyThreads;
                 if (x < n) {
                     const uint32_t y = desc ? n - 1 - x : x;
                     dst[lo + y] = kv[i];
@@ -352,7 +371,6 @@ __global__ __launch_bounds__(kFuseThreads) void unit_copy_kernel(MoveArgs a) {
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -1646,7 +1664,7 @@ static void launch_stage_t(const MoveArgs& a, int stage, uint32_t p, uint32_t gr
         else
             launch(fused_kernel<KT, HP>, grid, kFusedNT, 0, st, ev0, ev1, a);
     }
-    else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kFuseThreads, 0, st, ev0, ev1, a);
+    else if (stage == 5) launch(unit_copy_kernel<KT, HP>, grid, kCopyThreads, 0, st, ev0, ev1, a);
     else if (stage == 4) {
         const uint32_t kb = sizeof(typename Key<KT>::ukey);
         static bool rattr_set = false;
