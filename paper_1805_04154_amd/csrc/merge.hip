@@ -1048,6 +1048,24 @@ __device__ __forceinline__ uint32_t group_corank(const uint32_t* __restrict__ sm
     uint32_t h = k1 >= KA ? nx : rA + k1 * S;
     l = max(l, d > ny ? d - ny : 0u);
     h = min(h, min(d, nx));
+    // The sampled Y elements before the split are D - (sampled X elements).
+    // If the (D0 + 1)-th merged sample is an X element (k1 > k0) that is
+    // D0 - k0 whichever of D0, D0 + 1 D is; otherwise D0 - k0 or one more.
+    // Y's sample positions rC + j S bound the split from the other side, so
+    // the window searched is at most S wide when k1 > k0.
+    if (D0 >= 0 && D0 < (int64_t)(KA + KC)) {
+        const int64_t kyl = D0 - (int64_t)k0, kyh = k1 > k0 ? kyl : kyl + 1;
+        if (kyh < (int64_t)KC) {
+            // Y's sample kyh is not before the split: d - c <= rC + kyh S
+            const int64_t lo_c = (int64_t)d - rC - kyh * (int64_t)S;
+            if (lo_c > (int64_t)l) l = (uint32_t)lo_c;
+        }
+        if (kyl >= 1) {
+            // Y's sample kyl - 1 is before the split: d - c > rC + (kyl - 1) S
+            const int64_t hi_c = (int64_t)d - rC - (kyl - 1) * (int64_t)S - 1;
+            if (hi_c < (int64_t)h) h = (uint32_t)max<int64_t>(hi_c, (int64_t)l);
+        }
+    }
     return group_first(l, h, [&](uint32_t i) { return K::ord(X[i]) > K::ord(Y[d - 1 - i]); });
 }
 
