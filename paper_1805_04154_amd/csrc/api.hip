@@ -592,7 +592,7 @@ static ps_status run(const Call& c, const ps_options* opt, hipStream_t st) {
     // that many + 1 levels build the whole tree (the key bound of kMaxPass).
     const uint32_t peek_levels = std::max<uint32_t>(1, 2 * ilog2_floor(c.N));
     if (c.peek) {
-        ProfScope ps_(PS_PROF_TREE, 1 + peek_levels, c.N, st, c.prof);
+        ProfScope ps_(PS_PROF_TREE, 1 + (peek_levels + 1) / 2, c.N, st, c.prof);
         e = launch_peek_tree(ta, (PeekRange*)at(L.peek_f[0]), (PeekRange*)at(L.peek_f[1]), L.peek_cap, peek_levels,
                              st);
     } else {

@@ -179,7 +179,8 @@ hipError_t launch_tree_cost(const TreeArgs& a, hipStream_t st);
 struct PeekRange {
     uint32_t a, b, g, pad;  // leaves [a, b) of segment g
 };
-// Peeksort's tree, depths, node ranges and merge cost in `levels` launches.
+// Peeksort's tree, depths, node ranges and merge cost for depths below
+// `levels`, in 1 + ceil(levels / 2) launches.
 hipError_t launch_peek_tree(const TreeArgs& a, PeekRange* f0, PeekRange* f1, uint32_t cap, uint32_t levels,
                             hipStream_t st);
 hipError_t launch_node_ranges(const TreeArgs& a, hipStream_t st);

@@ -676,11 +676,12 @@ __global__ void pass_base_kernel(Counters* cnt) {
 // A[l..r] (first leaf A[l..e], last leaf A[s..r]) with m = l + floor((r-l)/2)
 // is cut after its first leaf if m <= e, before its last leaf if m >= s, and
 // otherwise at the nearer end of the leaf A[i..j] containing m: before it if
-// m - i < j - m, else after it.  One launch per level: level d reads the
-// ranges of depth d and writes their nodes and the ranges of depth d+1.
-// Node j (the cut, between leaves j-1 and j) gets the merge-pass key
-// P[j] = d + 1, so children (deeper) merge before their parent, exactly as
-// with node powers; boundaries that are not nodes keep P = 0.
+// m - i < j - m, else after it.  One launch per two depths: the launch for
+// depth d reads the ranges of depth d, writes the nodes of depths d and
+// d + 1 and the ranges of depth d + 2.  Node j (the cut of a range at depth
+// t, between leaves j-1 and j) gets the merge-pass key P[j] = t + 1, so
+// children (deeper) merge before their parent, exactly as with node powers;
+// boundaries that are not nodes keep P = 0.
 
 // lower_bound over starts[0..n): first k with starts[k] >= v.
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t n, uint64_t v) {
@@ -719,11 +720,34 @@ __global__ __launch_bounds__(kThreads) void peek_roots_kernel(const uint32_t* __
     }
 }
 
+// The cut of a range of whole leaves [a, b), b - a >= 2 (Alg. PeekSort).
+__device__ __forceinline__ uint32_t peek_cut(const uint32_t* __restrict__ starts, uint32_t a, uint32_t b) {
+    const uint32_t l = starts[a], r = starts[b] - 1;
+    const uint32_t e = starts[a + 1] - 1, s = starts[b - 1];
+    const uint32_t m = l + (r - l) / 2;
+    if (m <= e) return a + 1;
+    if (m >= s) return b - 1;
+    // leaf kk of (a, b) with starts[kk] <= m < starts[kk+1]
+    uint32_t lo = a, hi = b;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (starts[mid] <= m) lo = mid; else hi = mid;
+    }
+    const uint32_t i = starts[lo], j = starts[lo + 1] - 1;
+    return (m - i < j - m) ? lo : lo + 1;
+}
+
+// Two depths per launch: each range of depth d is cut, then each of its
+// parts with two or more leaves (depth d + 1, if that depth can hold a node)
+// is cut as well, and the parts of those with two or more leaves are the
+// ranges of depth d + 2.  Node j = cut of a range at depth t gets P[j] =
+// t + 1, its depth, its leaf range and size; a part of one leaf gets its
+// leaf depth.  Halves the dependent launches of the level-by-level build.
 __global__ __launch_bounds__(kThreads) void peek_level_kernel(const uint32_t* __restrict__ starts,
                                                               Counters* __restrict__ cnt,
                                                               const PeekRange* __restrict__ Fin,
                                                               PeekRange* __restrict__ Fout, uint32_t cap,
-                                                              uint32_t d, uint8_t* __restrict__ P,
+                                                              uint32_t d, uint32_t levels, uint8_t* __restrict__ P,
                                                               uint8_t* __restrict__ node_depth,
                                                               uint8_t* __restrict__ leaf_depth,
                                                               uint32_t* __restrict__ Lf, uint32_t* __restrict__ Rt,
@@ -732,40 +756,44 @@ __global__ __launch_bounds__(kThreads) void peek_level_kernel(const uint32_t* __
     __shared__ uint32_t sh[kWaves];
     __shared__ uint32_t base_sh;
     const uint32_t nin = min(cnt->peek_count[d], cap);
+    // records node `cut` of the range [a, b) at depth t; returns its size
+    auto node = [&](uint32_t a, uint32_t b, uint32_t cut, uint32_t t) {
+        const uint32_t size = starts[b] - starts[a];
+        P[cut] = (uint8_t)(t + 1);
+        node_depth[cut] = (uint8_t)t;
+        Lf[cut] = a;
+        Rt[cut] = b;
+        nsize[cut] = size;
+        if (cut - a == 1) leaf_depth[a] = (uint8_t)(t + 1);
+        if (b - cut == 1) leaf_depth[cut] = (uint8_t)(t + 1);
+        return size;
+    };
     for (uint32_t k0 = blockIdx.x * kThreads; k0 < nin; k0 += gridDim.x * kThreads) {
         const uint32_t k = k0 + threadIdx.x;
         const bool valid = k < nin;
-        uint32_t a = 0, b = 0, cut = 0, g = 0, size = 0;
+        uint32_t g = 0, size = 0, nout = 0;
+        uint32_t oa[4], ob[4];
         if (valid) {
             const PeekRange R = Fin[k];
-            a = R.a;
-            b = R.b;
             g = R.g;
-            const uint32_t l = starts[a], r = starts[b] - 1;
-            const uint32_t e = starts[a + 1] - 1, s = starts[b - 1];
-            const uint32_t m = l + (r - l) / 2;
-            if (m <= e) {
-                cut = a + 1;
-            } else if (m >= s) {
-                cut = b - 1;
-            } else {
-                // leaf kk of (a, b) with starts[kk] <= m < starts[kk+1]
-                uint32_t lo = a, hi = b;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (starts[mid] <= m) lo = mid; else hi = mid;
+            const uint32_t cut = peek_cut(starts, R.a, R.b);
+            size = node(R.a, R.b, cut, d);
+            const uint32_t pa[2] = {R.a, cut}, pb[2] = {cut, R.b};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (pb[h] - pa[h] >= 2 && d + 1 < levels) {
+                    const uint32_t c2 = peek_cut(starts, pa[h], pb[h]);
+                    size += node(pa[h], pb[h], c2, d + 1);
+                    if (c2 - pa[h] >= 2) {
+                        oa[nout] = pa[h];
+                        ob[nout++] = c2;
+                    }
+                    if (pb[h] - c2 >= 2) {
+                        oa[nout] = c2;
+                        ob[nout++] = pb[h];
+                    }
                 }
-                const uint32_t i = starts[lo], j = starts[lo + 1] - 1;
-                cut = (m - i < j - m) ? lo : lo + 1;
             }
-            size = starts[b] - l;
-            P[cut] = (uint8_t)(d + 1);
-            node_depth[cut] = (uint8_t)d;
-            Lf[cut] = a;
-            Rt[cut] = b;
-            nsize[cut] = size;
-            if (cut - a == 1) leaf_depth[a] = (uint8_t)(d + 1);
-            if (b - cut == 1) leaf_depth[cut] = (uint8_t)(d + 1);
         }
         // M = sum of merge result sizes, per segment: one atomic per wave for
         // the lanes of the first active lane's segment, one per other lane
@@ -782,15 +810,14 @@ __global__ __launch_bounds__(kThreads) void peek_level_kernel(const uint32_t* __
                 if (valid && !same) atomicAdd(&mc[g], (unsigned long long)size);
             }
         }
-        const uint32_t nl = valid && cut - a >= 2, nr = valid && b - cut >= 2;
         uint32_t total;
-        const uint32_t pos = block_excl_sum(nl + nr, sh, &total);
-        if (threadIdx.x == 0) base_sh = total ? atomicAdd(&cnt->peek_count[d + 1], total) : 0u;
+        const uint32_t pos = block_excl_sum(nout, sh, &total);
+        if (threadIdx.x == 0) base_sh = total ? atomicAdd(&cnt->peek_count[d + 2], total) : 0u;
         __syncthreads();
         const uint32_t base = base_sh + pos;
         __syncthreads();
-        if (nl && base < cap) Fout[base] = PeekRange{a, cut, g, 0};
-        if (nr && base + nl < cap) Fout[base + nl] = PeekRange{cut, b, g, 0};
+        for (uint32_t q = 0; q < nout; ++q)
+            if (base + q < cap) Fout[base + q] = PeekRange{oa[q], ob[q], g, 0};
     }
 }
 
@@ -861,11 +888,11 @@ hipError_t launch_peek_tree(const TreeArgs& a, PeekRange* f0, PeekRange* f1, uin
     hipLaunchKernelGGL(peek_roots_kernel, dim3(grid_for(a.nseg, 1024)), dim3(kThreads), 0, st, a.starts, a.offsets,
                        a.nseg, a.cnt, f0, cap, a.P, a.leaf_depth);
     const uint32_t g = grid_for(cap, 2048);
-    for (uint32_t d = 0; d < levels; ++d) {
-        PeekRange* fin = (d & 1) ? f1 : f0;
-        PeekRange* fout = (d & 1) ? f0 : f1;
+    for (uint32_t d = 0; d < levels; d += 2) {
+        PeekRange* fin = (d & 2) ? f1 : f0;
+        PeekRange* fout = (d & 2) ? f0 : f1;
         hipLaunchKernelGGL(peek_level_kernel, dim3(g), dim3(kThreads), 0, st, a.starts, a.cnt, fin, fout, cap, d,
-                           a.P, a.node_depth, a.leaf_depth, a.Lf, a.Rt, a.nsize, (unsigned long long*)a.mc);
+                           levels, a.P, a.node_depth, a.leaf_depth, a.Lf, a.Rt, a.nsize, (unsigned long long*)a.mc);
     }
     return hipGetLastError();
 }
