@@ -71,7 +71,7 @@ constexpr int kFuseItems = 8;
 constexpr int kFuse = kFuseThreads * kFuseItems;  // 4096
 // A fused subtree with at least this many leaves is sorted by the block
 // radix sort instead of level-by-level merges (any key width: 8-byte keys
-// need about 100 KiB of LDS, one block per CU, and still win on permutations);
+// need 108 KiB of LDS, one block per CU, and still win on permutations);
 // smaller ones hold at most kFuseRadixMinLeaves - 2 merges.
 constexpr uint32_t kFuseRadixMinLeaves = 8;
 __host__ __device__ constexpr bool fuse_by_radix(uint32_t key_bytes, uint32_t nleaves) {

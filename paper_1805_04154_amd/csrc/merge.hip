@@ -152,11 +152,11 @@ __global__ __launch_bounds__(kThreads) void big_leaf_kernel(MoveArgs a) {
 // eight ballots, and a per-wave counter per digit carries the count from one
 // slot to the next, so ranks follow the current order (stability).  The
 // per-wave counts then become destinations by a scan over (digit, wave).
-// hist: kFuseWaves x 256 counters; ranks stay in registers.  Returns true if the
+// hist: kFuseWaves x 256 counters, rank: kFuse entries.  Returns true if the
 // result ended in tk/tp.  Block-uniform; all threads call.
 template <class U, bool HP>
 __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uint32_t* tp, uint32_t n,
-                                                 uint16_t* hist, uint32_t* sh,
+                                                 uint16_t* hist, uint16_t* rank, uint32_t* sh,
                                                  unsigned long long* red) {
     constexpr int BITS = 8 * sizeof(U);
     const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -181,12 +181,8 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
     for (int s = 0; s < BITS; s += 8) {
         if (((diff >> s) & (U)0xFF) == 0) continue;  // every key has the same digit
         for (uint32_t i = lane; i < 256; i += 64) hw[i] = 0;
-        // Each slot's digit, its rank among the slot's lanes with that digit
-        // and their count (independent across slots), then the per-wave
-        // counters in slot order; ranks stay in registers for the scatter.
-        uint32_t dg[kFuseItems], rk[kFuseItems];
-        uint32_t pc[kFuseItems];
-#pragma unroll
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
         for (int q = 0; q < kFuseItems; ++q) {
             const uint32_t x = w * 512 + q * 64 + lane;
             const bool valid = x < n;
@@ -197,18 +193,12 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
                 const uint64_t bb = __ballot((d >> b) & 1u);
                 peers &= ((d >> b) & 1u) ? bb : ~bb;
             }
-            dg[q] = d;
-            rk[q] = (uint32_t)__popcll(peers & lt);
-            pc[q] = valid ? (uint32_t)__popcll(peers) : 0u;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < kFuseItems; ++q) {
-            const uint32_t base = hw[dg[q]];
+            const uint32_t before = (uint32_t)__popcll(peers & lt);
+            const uint32_t base = valid ? hw[d] : 0u;
             __builtin_amdgcn_wave_barrier();
-            if (pc[q] != 0 && rk[q] == 0) hw[dg[q]] = (uint16_t)(base + pc[q]);
+            if (valid && before == 0) hw[d] = (uint16_t)(base + (uint32_t)__popcll(peers));
             __builtin_amdgcn_wave_barrier();
-            rk[q] += base;
+            if (valid) rank[x] = (uint16_t)(base + before);
         }
         __syncthreads();
         // hist[w][d] := elements before (digit d, wave w) in the pass's order
@@ -229,8 +219,9 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
         for (int q = 0; q < kFuseItems; ++q) {
             const uint32_t x = w * 512 + q * 64 + lane;
             if (x < n) {
-                const uint32_t dst = hw[dg[q]] + rk[q];
-                tk[dst] = sk[x];
+                const U key = sk[x];
+                const uint32_t dst = hw[(uint32_t)((key >> s) & (U)0xFF)] + rank[x];
+                tk[dst] = key;
                 if (HP) tp[dst] = sp[x];
             }
         }
@@ -247,9 +238,9 @@ __device__ __forceinline__ bool block_radix_sort(U* sk, uint32_t* sp, U* tk, uin
 }
 
 // LDS of fused_radix_kernel: keys and payloads twice, the per-wave digit
-// counters, and a 128-byte header (wave totals, a reduction word).
+// counters, the ranks, and a 128-byte header (wave totals, a reduction word).
 __host__ __device__ constexpr uint32_t radix_lds_bytes(uint32_t key_bytes, bool hp) {
-    return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2;
+    return 128 + 2 * kFuse * (key_bytes + (hp ? 4u : 0u)) + kFuseWaves * 256 * 2 + kFuse * 2;
 }
 
 // Fused subtrees with many leaves: every merge in a subtree is
@@ -269,6 +260,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
     uint32_t* sp = reinterpret_cast<uint32_t*>(tk + kFuse);
     uint32_t* tp = sp + (HP ? kFuse : 0);
     uint16_t* hist = reinterpret_cast<uint16_t*>(tp + (HP ? kFuse : 0));
+    uint16_t* rank = hist + kFuseWaves * 256;
     const uint32_t nunits = a.cnt->nunit[kUnitRadix];
     const uint32_t tid = threadIdx.x;
     for (uint32_t v = blockIdx.x; v < nunits; v += gridDim.x) {
@@ -301,7 +293,7 @@ __global__ __launch_bounds__(kFuseThreads) void fused_radix_kernel(MoveArgs a) {
             }
         }
         __syncthreads();
-        const bool alt = block_radix_sort<U, HP>(sk, sp, tk, tp, n, hist, sh, red);
+        const bool alt = block_radix_sort<U, HP>(sk, sp, tk, tp, n, hist, rank, sh, red);
         const U* ok = alt ? tk : sk;
         const uint32_t* op = alt ? tp : sp;
 #pragma unroll
