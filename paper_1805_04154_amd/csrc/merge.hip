@@ -1339,9 +1339,11 @@ __global__ __launch_bounds__(NT) void merge_pass_cr_kernel(MoveArgs a, uint32_t 
 // NT threads x IT outputs per group of tiles.  A group reads its part of
 // each input run (A, B, C, D; B or D is empty when that child is an input)
 // into LDS, merges A with B and C with D (the absorbed children's parts),
-// then the two results, and writes its part of the node.
+// then the two results, and writes its part of the node.  Each merge step
+// keeps both run heads in registers and reads only the one that advanced;
+// six waves per SIMD leave room for that without spills.
 template <int KT, bool HP, int NT, int IT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void merge_quad_kernel(MoveArgs a, uint32_t p) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void merge_quad_kernel(MoveArgs a, uint32_t p) {
     constexpr int TILE = NT * IT;
     using K = Key<KT>;
     using U = typename K::ukey;
@@ -1463,6 +1465,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                 const uint32_t dg = dx - base;
                 const uint32_t l = lds_corank<kLog2QuadTile>(sm.sk, base, n1, base + n1, n2, dg);
                 uint32_t i1 = base + l, e1 = base + n1, i2 = base + n1 + (dg - l), e2 = base + n1 + n2;
+                // the two run heads stay in registers (reads clamped inside
+                // the tile); each step reads only the head that advanced
+                U k1 = sm.sk[lpad(min(i1, nt - 1))], k2 = sm.sk[lpad(min(i2, nt - 1))];
 #pragma unroll
                 for (int i = 0; i < IT; ++i) {
                     const uint32_t x = dx + i;
@@ -1472,15 +1477,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
                             e1 = ncl;
                             i2 = ncl;
                             e2 = nt;
+                            k1 = sm.sk[lpad(min(i1, nt - 1))];
+                            k2 = sm.sk[lpad(min(i2, nt - 1))];
                         }
-                        // both heads read (clamped inside the tile), then selected: no branch
-                        const U k1 = sm.sk[lpad(min(i1, nt - 1))], k2 = sm.sk[lpad(min(i2, nt - 1))];
                         const bool take1 = (i2 >= e2) | ((i1 < e1) & (k1 <= k2));
                         const uint32_t s = take1 ? i1 : i2;
                         kr[i] = take1 ? k1 : k2;
                         if (HP) pr[i] = sm.sp[lpad(s)];
                         i1 += take1 ? 1u : 0u;
                         i2 += take1 ? 0u : 1u;
+                        if (i + 1 < IT) {
+                            const U v = sm.sk[lpad(min(take1 ? i1 : i2, nt - 1))];
+                            k1 = take1 ? v : k1;
+                            k2 = take1 ? k2 : v;
+                        }
                     }
                 }
             }
@@ -1501,16 +1511,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void me
         if (dx < nt) {
             const uint32_t l = lds_corank<kLog2QuadTile>(sm.sk, 0, nl, nl, nrp, dx);
             uint32_t ia = l, ib = nl + (dx - l);
+            U ka = sm.sk[lpad(min(ia, nt - 1))], kb = sm.sk[lpad(min(ib, nt - 1))];
 #pragma unroll
             for (int i = 0; i < IT; ++i) {
                 if (dx + i < nt) {
-                    const U ka = sm.sk[lpad(min(ia, nt - 1))], kb = sm.sk[lpad(min(ib, nt - 1))];
                     const bool take_a = (ib >= nt) | ((ia < nl) & (ka <= kb));
                     const uint32_t s = take_a ? ia : ib;
                     kr[i] = take_a ? ka : kb;
                     if (HP) pr[i] = sm.sp[lpad(s)];
                     ia += take_a ? 1u : 0u;
                     ib += take_a ? 0u : 1u;
+                    if (i + 1 < IT) {
+                        const U v = sm.sk[lpad(min(take_a ? ia : ib, nt - 1))];
+                        ka = take_a ? v : ka;
+                        kb = take_a ? kb : v;
+                    }
                 }
             }
         }
