@@ -349,6 +349,10 @@ __global__ __launch_bounds__(kCopyThreads) __attribute__((amdgpu_waves_per_eu(si
             const raw k1 = __shfl(kv[0], 1);  // n > kMaxMinRun: elements 0 and 1 exist
             if (tid == 0) desc_sh[round & 1] = K::ord(k1) < K::ord(kv[0]) ? 1u : 0u;
         }
+        // A run reversed in place: each wave's loads are complete before it
+        // reaches the barrier, so no wave's stores can overtake another's
+        // loads (the barrier alone does not wait for loads in flight).
+        if (in_place) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         const bool desc = desc_sh[round & 1] != 0;
         if (desc || !in_place) {
