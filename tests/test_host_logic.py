@@ -155,6 +155,52 @@ def test_every_node_power_is_within_the_pass_bound(w):
     assert int(ref.powers.max()) >= pass_bound(1 << 16, w) - 1
 
 
+def fused_units(starts: np.ndarray, merges: np.ndarray, n: int, fuse: int = 4096):
+    """Fused subtrees from the oracle's merge tree: the children of at most
+    ``fuse`` elements of nodes larger than that (and the whole array if it
+    is that small), as (elements, leaves)."""
+    s = starts.astype(np.int64)
+    leaves = lambda lo, hi: int(np.searchsorted(s, hi) - np.searchsorted(s, lo))
+    out = []
+    for lo, mid, hi in merges.astype(np.int64):
+        if hi - lo > fuse:
+            for a, b in ((lo, mid), (mid, hi)):
+                if b - a <= fuse:
+                    out.append((int(b - a), leaves(a, b)))
+    if n <= fuse and n > 0:
+        out.append((n, len(s) - 1))
+    return out
+
+
+@pytest.mark.parametrize("w", [1, 24, 64])
+def test_fused_subtree_lists_fit_their_capacities(w):
+    # The workspace holds one list per kernel that forms fused subtrees:
+    # single natural runs longer than any min-run (at most n / 65 + 1 of
+    # them), subtrees of eight or more leaves (at most r1 / 8 + 1) and the
+    # rest (at most r1), with r1 = rmax + 1 and rmax = n / max(w, 2) + 2 the
+    # leaf bound of the layout for one segment.
+    import math
+    import oracle
+    rng = W.make_rng(79)
+    seen = {"copy": 0, "few": 0, "radix": 0}
+    for n in (70, 4096, 5000, 50001, 300000):
+        for v in (W.random_permutation(rng, n), W.random_runs(rng, n, 40.0, 0.25),
+                  W.random_runs(rng, n, max(2.0, math.sqrt(n)), 0.25), W.random_runs(rng, n, 3000.0, 0.1),
+                  np.arange(n)[::-1].copy()):
+            ref = oracle.powersort(np.asarray(v).astype(np.int32), None, min_run=w)
+            rmax = min(n, n // max(w, 2) + 2)
+            r1 = rmax + 1
+            caps = {"copy": min(r1, n // 65 + 1), "radix": r1 // 8 + 1, "few": r1}
+            count = {"copy": 0, "few": 0, "radix": 0}
+            for size, nl in fused_units(ref.starts, ref.merges, n):
+                kind = "copy" if (nl == 1 and size > 64) else ("radix" if nl >= 8 else "few")
+                count[kind] += 1
+            for k in count:
+                assert count[k] <= caps[k], (n, w, k, count[k], caps[k])
+                seen[k] += count[k]
+    assert all(seen[k] > 0 for k in seen)  # every kind occurs
+
+
 def test_arena_allocator_first_fit_and_coalescing():
     from paper_1805_04154_amd.serving import ALIGN, ArenaAllocator
     a = ArenaAllocator(10 * ALIGN)
