@@ -637,7 +637,7 @@ __device__ __forceinline__ void fused_stage(const MoveArgs& a, const UnitRec ur,
 // current one is merged: direct loads fill an unpadded staging copy in LDS,
 // leaf formation reads it and writes the padded working copy, and the loads
 // of the next subtree are issued right after.  The leaves and merges are the
-// same as fused_kernel's.  LDS: about 68 KiB with a payload, two blocks per CU.
+// same as fused_kernel's.  LDS: about 69 KiB with a payload, two blocks per CU.
 template <int KT, bool HP>
 __global__ __launch_bounds__(kFusedNT) __attribute__((amdgpu_waves_per_eu(8))) void fused_staged_kernel(MoveArgs a) {
     constexpr int NT = kFusedNT, IT = kFuse / kFusedNT;
